@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the scattering self-energy kernel on one MI355X.
+
+One step = one sse_compute of the device-scale problem (NA=1024, NB=4,
+Norb=10, Nkz=Nqz=7, NE=1000, Nw=30; Sigma [7, 1000, 1024, 10, 10]) for both
+components (lesser and greater) in binary64, inputs resident in HBM.  Prints
+one JSON line; see the design doc for the flop and byte accounting.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 fp64 FMA lanes/clk x 2
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", action="store_true",
+                    help="print a progress line per step (for profiler runs)")
+    return ap.parse_args()
+
+
+def ci95(xs):
+    if len(xs) < 2:
+        return 0.0
+    return 1.96 * statistics.stdev(xs) / math.sqrt(len(xs))
+
+
+def cpu_baseline(prob, seed, target_s):
+    """The oracle (unchanged) on a bounded sample of output blocks of the same
+    workload: all k, sampled energies (incl. the edges) and atoms."""
+    import numpy as np
+    import oracle
+    import ssegen
+    from tests import gpu_util as gu
+    cores = len(os.sched_getaffinity(0))
+    # calibrate on a small sample, then size the timed sample to ~target_s
+    blocks_all = gu.sample_blocks(prob, 11, n_e=16, n_a=64)
+    rng = np.random.default_rng(5)
+    rng.shuffle(blocks_all)
+    neigh = ssegen.neigh(seed, prob.NA, prob.NB)
+    dH = ssegen.dH(seed, prob.NA, prob.NB, prob.Norb)
+    D = ssegen.D(seed, 0, prob.Nqz, prob.Nw, prob.NA, prob.NB)
+
+    def run(blocks):
+        need = oracle.needed_g_blocks(neigh, prob.shifts(), prob.Nkz, prob.Nqz, prob.NE,
+                                      prob.NA, blocks)
+        Gb = ssegen.G_flat_blocks(seed, 0, prob.Norb, need)
+        gslot = np.full(prob.Nkz * prob.NE * prob.NA, -1, dtype=np.int64)
+        gslot[need] = np.arange(need.size)
+        t0 = time.perf_counter()
+        oracle.sigma(neigh, dH, Gb, D, prob.shifts(), prob.Nkz, prob.NE, blocks=blocks,
+                     gslot=gslot, nthreads=cores)
+        return time.perf_counter() - t0
+
+    n0 = min(len(blocks_all), 4 * cores)
+    t_cal = run(blocks_all[:n0])
+    n = int(min(len(blocks_all), max(n0, n0 * target_s / max(t_cal, 1e-3))))
+    t = run(blocks_all[:n])
+    per_block_alg = prob.flops() / (prob.Nkz * prob.NE * prob.NA)
+    per_block_plain = prob.flops_plain() / (prob.Nkz * prob.NE * prob.NA)
+    return {
+        "value": round(per_block_alg * n / t / 1e9, 3),
+        "unit": "GFLOP/s (algorithmic-equivalent)",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{n} output blocks of one component (all 7 k x 16 energies incl. edges x "
+                  f"64 atoms, shuffled), {t:.1f} s",
+        "blocks_per_s": round(n / t, 2),
+        "plain_gflops": round(per_block_plain * n / t / 1e9, 3),
+        "extrapolated_full_job_s": round(t / n * prob.Nkz * prob.NE * prob.NA * 2, 1),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
+              "(every output block is independent; see DESIGN.md for how the path shards).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1912_08810_amd import configs, sse
+    from ssegen.device_problem import DeviceProblem
+
+    prob = configs.DEVICE
+    seed = configs.SEED
+    ncomp = 2
+    dp = DeviceProblem(prob, seed, ncomp=ncomp)
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                         ncomp=ncomp, prec=sse.FP64)
+    plan = sse.sse_plan(desc, prob.shifts())
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+
+    for i in range(args.warmup):
+        step()
+        if args.profile_steps:
+            print(f"warmup {i} done", flush=True)
+    torch.cuda.synchronize()
+    times = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        if args.profile_steps:
+            print(f"step {i}: {times[-1]*1e3:.1f} ms", flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    med = statistics.median(times)
+    flops_step = prob.flops() * ncomp
+    launches_per_step = ncomp
+    t_launch = med / launches_per_step
+    achieved_tf = prob.flops() / t_launch / 1e12
+    out = {
+        "metric": "SSE complex GFLOP/s (algorithmic, binary64) at device scale",
+        "value": round(flops_step / med / 1e9, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(med * 1e3, 3),
+        "ms_per_step_ci95": round(ci95(times) * 1e3, 3),
+        "wall_s_timed": round(wall, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Philox inputs: anti-Hermitian G and D~, N(0,1) dH, "
+                "random neighbour table without self)",
+        "config": {"workload": "Sigma lesser+greater, NA=1024 NB=4 Norb=10 Nkz=Nqz=7 NE=1000 "
+                               "Nw=30 (s_w=w+1), complex128",
+                   "ncomp": ncomp, "output_blocks_per_s": round(
+                       prob.Nkz * prob.NE * prob.NA * ncomp / med, 1)},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tf, 3),
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_sse_fp64", "launch_ms": round(t_launch * 1e3, 3)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

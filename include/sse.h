@@ -1,0 +1,153 @@
+/*
+ * sse.h -- C ABI of libsse.so, the MI355X (gfx950) electron scattering
+ * self-energy library.
+ *
+ * Operation (Ziogas et al., SC'19, Sec. 2, Eq. (3); tensor shapes from the
+ * typed Sigma program of Sec. 3): for every momentum k, energy e and atom a,
+ *
+ *   Sigma[k, e, a] = alpha * sum_{b < NB} sum_{q < Nqz} sum_{w < Nw} sum_{i, j < N3D}
+ *       Dt[q, w, a, b, i, j] * dH[a, b, i] . G[(k - q) mod Nkz, e - s_w, f] . dH[a, b, j]^T
+ *
+ * where f = neigh[a, b] (the neighbour indirection of Sec. 4.1), s is the
+ * caller's integer energy-shift table (s_w = w + 1 on a uniform grid), terms
+ * with e - s_w outside [0, NE) are zero, and Dt is the phonon Green's function
+ * already combined as D_ba - D_bb - D_aa + D_ab (Eq. (3); Sec. 4.2 lists it
+ * as a kernel input).  The result overwrites Sigma.  Only the diagonal blocks
+ * of Sigma are produced, as in the paper (Sec. 2).
+ *
+ * Memory.  Every tensor is caller-owned device memory, contiguous, row-major,
+ * complex values interleaved (re, im):
+ *   neigh int32   [NA, NB]
+ *   dH    float64 [NA, NB, N3D, Norb, Norb]
+ *   G     complex [ncomp][Nkz, NE, NA, Norb, Norb]
+ *   Dt    complex [ncomp][Nqz, Nw, NA, NB, N3D, N3D]
+ *   Sigma complex [ncomp][Nkz, NE, NA, Norb, Norb]
+ * "complex" is complex128 (16 bytes) for SSE_FP64 and complex64 (8 bytes) for
+ * SSE_FP32 and SSE_BF16X3.  With ncomp = 2 the lesser and greater components
+ * are stacked on a leading axis; each is computed from its own G and Dt.
+ * The workspace is caller-owned device memory of at least the size that
+ * sse_plan reports; the library keeps no pointer after the call (or, for
+ * sse_submit, after sse_poll/sse_wait has returned something other than
+ * SSE_PENDING).  A plan owns only small tables (shift and tile tables) and
+ * frees them in sse_plan_destroy.
+ *
+ * Errors.  Every function returns a status; nothing aborts and no exception
+ * crosses the ABI.  sse_last_error() gives a text for the calling thread's
+ * last non-OK status.  A neighbour index outside [0, NA) is detected on the
+ * device: the kernels skip that neighbour (nothing out of bounds is read) and
+ * the call reports SSE_ERR_NEIGH.
+ *
+ * Threading.  Plans are immutable after creation and may be shared between
+ * threads.  sse_submit, sse_poll and sse_wait are thread-safe.  Calls that
+ * share one workspace must not overlap in time.
+ */
+#ifndef SSE_H
+#define SSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSE_OK = 0,
+    SSE_PENDING = 1,        /* sse_poll: the submission is still running */
+    SSE_ERR_ARG = 2,        /* NULL pointer, bad enum, workspace too small, unknown ticket */
+    SSE_ERR_SHAPE = 3,      /* a dimension outside the supported range (see sse_plan) */
+    SSE_ERR_NEIGH = 4,      /* a neighbour index outside [0, NA) was found on the device */
+    SSE_ERR_NOMEM = 5,      /* a host or small device allocation of the library failed */
+    SSE_ERR_BUSY = 6,       /* too many submissions in flight */
+    SSE_ERR_TOLERANCE = 7,  /* sse_check: sampled error above the caller's tolerance */
+    SSE_ERR_DEVICE = 8,     /* a HIP runtime call failed (the text names it) */
+    SSE_ERR_UNSUPPORTED = 9 /* valid request that this build does not implement */
+} sse_status;
+
+typedef enum {
+    SSE_FP64 = 0,  /* complex128 storage, binary64 arithmetic throughout */
+    SSE_FP32 = 1,  /* complex64 storage; tap products on fp32 MFMA, fp32 accumulation
+                      within one qz row of taps, binary64 accumulation across rows,
+                      neighbours and in the dH sandwich */
+    SSE_BF16X3 = 2 /* complex64 storage; tap products as bf16 hi*hi + hi*lo + lo*hi on
+                      MFMA with fp32 accumulation within one qz row, binary64 beyond */
+} sse_precision;
+
+typedef struct {
+    int32_t NA;    /* atoms, >= 1 */
+    int32_t NB;    /* neighbours per atom, 1..50 (Sec. 2, typical parameter table) */
+    int32_t Norb;  /* orbitals per atom, 1..30 (same table) */
+    int32_t N3D;   /* vibration directions, must be 3 */
+    int32_t Nkz;   /* electron momenta, >= 1 */
+    int32_t Nqz;   /* phonon momenta, 1..Nkz (same momentum grid, periodic) */
+    int32_t NE;    /* energies, >= 1 */
+    int32_t Nw;    /* phonon frequencies, 1..128 */
+    int32_t ncomp; /* 1, or 2 = lesser and greater stacked */
+    int32_t prec;  /* sse_precision */
+    double alpha_re, alpha_im; /* prefactor; Eq. (3) is alpha = i (0 + 1i) */
+} sse_desc;
+
+/* One instance's device pointers (see the layout above). */
+typedef struct {
+    const int32_t *neigh;
+    const double *dH;
+    const void *G;
+    const void *Dt;
+    void *Sigma;
+} sse_args;
+
+typedef struct sse_plan_s *sse_plan_t;
+
+/*
+ * Validate a problem and build a plan.  w_shift: host array [Nw] of energy
+ * index shifts, |s_w| < NE (may be negative; need not be sorted).
+ * *workspace_bytes receives the device workspace size every call with this
+ * plan needs.  SSE_ERR_SHAPE if NA, Nkz, NE < 1, NB outside 1..50, Norb outside
+ * 1..30, N3D != 3, Nqz outside 1..Nkz, Nw outside 1..128, ncomp not 1 or 2, a
+ * shift out of range, or a tensor larger than 2^62 elements.
+ */
+sse_status sse_plan(const sse_desc *desc, const int32_t *w_shift, sse_plan_t *plan,
+                    size_t *workspace_bytes);
+
+/*
+ * Batch plan (persistent launch): n instances of uneven sizes computed by one
+ * persistent kernel launch per component.  descs[t] and w_shift[t] as in
+ * sse_plan; all instances must share Norb, N3D, ncomp, prec and alpha.
+ * Per instance, the tile shape (energies per tile) comes from the plan's
+ * size-bucket tuning table (sse_tune_set).
+ */
+sse_status sse_plan_batch(const sse_desc *descs, const int32_t *const *w_shift, int32_t n,
+                          sse_plan_t *plan, size_t *workspace_bytes);
+
+/*
+ * Compute Sigma for a single-instance plan; returns when the result is in
+ * Sigma (the work runs on `stream`, a hipStream_t; NULL = the null stream).
+ */
+sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
+                       const void *Dt, void *Sigma, void *workspace, size_t workspace_bytes,
+                       void *stream);
+
+/*
+ * Enqueue the computation for every instance of the plan (args has one entry
+ * per instance) on `stream` and return at once with a ticket.
+ */
+sse_status sse_submit(sse_plan_t plan, const sse_args *args, void *workspace,
+                      size_t workspace_bytes, void *stream, uint64_t *ticket);
+
+/* SSE_PENDING while the submission runs, else its final status (the ticket is
+ * then released; polling it again gives SSE_ERR_ARG). */
+sse_status sse_poll(uint64_t ticket);
+
+/* Block until the submission ends; returns its final status and releases the ticket. */
+sse_status sse_wait(uint64_t ticket);
+
+void sse_plan_destroy(sse_plan_t plan);
+
+/* Text for the calling thread's last non-OK status ("" if none). */
+const char *sse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSE_H */

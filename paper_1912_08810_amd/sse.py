@@ -1,0 +1,175 @@
+"""Thin ctypes binding of libsse.so (include/sse.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels.  Tensors are
+passed as device pointers (torch tensors' ``data_ptr()`` or plain ints) and
+streams as ``hipStream_t`` handles (``torch.cuda.current_stream().cuda_stream``
+under ROCm).  Importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsse.so")
+
+OK, PENDING, ERR_ARG, ERR_SHAPE, ERR_NEIGH, ERR_NOMEM, ERR_BUSY, ERR_TOLERANCE, ERR_DEVICE, \
+    ERR_UNSUPPORTED = range(10)
+FP64, FP32, BF16X3 = 0, 1, 2
+STATUS_NAMES = ["SSE_OK", "SSE_PENDING", "SSE_ERR_ARG", "SSE_ERR_SHAPE", "SSE_ERR_NEIGH",
+                "SSE_ERR_NOMEM", "SSE_ERR_BUSY", "SSE_ERR_TOLERANCE", "SSE_ERR_DEVICE",
+                "SSE_ERR_UNSUPPORTED"]
+
+
+class sse_desc(ctypes.Structure):
+    _fields_ = [("NA", ctypes.c_int32), ("NB", ctypes.c_int32), ("Norb", ctypes.c_int32),
+                ("N3D", ctypes.c_int32), ("Nkz", ctypes.c_int32), ("Nqz", ctypes.c_int32),
+                ("NE", ctypes.c_int32), ("Nw", ctypes.c_int32), ("ncomp", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("alpha_re", ctypes.c_double),
+                ("alpha_im", ctypes.c_double)]
+
+
+class sse_args(ctypes.Structure):
+    _fields_ = [("neigh", ctypes.c_void_p), ("dH", ctypes.c_void_p), ("G", ctypes.c_void_p),
+                ("Dt", ctypes.c_void_p), ("Sigma", ctypes.c_void_p)]
+
+
+class SSEError(RuntimeError):
+    def __init__(self, status: int, where: str, text: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < 10 else status}: {text}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp = c.c_void_p
+    L.sse_plan.argtypes = [c.POINTER(sse_desc), vp, c.POINTER(vp), c.POINTER(c.c_size_t)]
+    L.sse_plan_batch.argtypes = [c.POINTER(sse_desc), c.POINTER(vp), c.c_int32, c.POINTER(vp),
+                                 c.POINTER(c.c_size_t)]
+    L.sse_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
+    L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
+                             c.POINTER(c.c_uint64)]
+    L.sse_poll.argtypes = [c.c_uint64]
+    L.sse_wait.argtypes = [c.c_uint64]
+    L.sse_plan_destroy.argtypes = [vp]
+    L.sse_plan_destroy.restype = None
+    L.sse_last_error.restype = c.c_char_p
+    for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_submit, L.sse_poll, L.sse_wait):
+        f.restype = c.c_int
+    return L
+
+
+lib = _load()
+
+# Every symbol include/sse.h declares (checked by the CPU test of the library).
+EXPORTS = ["sse_plan", "sse_plan_batch", "sse_compute", "sse_submit", "sse_poll", "sse_wait",
+           "sse_plan_destroy", "sse_last_error"]
+
+
+def last_error() -> str:
+    return lib.sse_last_error().decode()
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise SSEError(st, where, last_error())
+    return st
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def make_desc(NA, NB, Norb, Nkz, Nqz, NE, Nw, ncomp=1, prec=FP64, alpha=1j, N3D=3):
+    alpha = complex(alpha)
+    return sse_desc(NA, NB, Norb, N3D, Nkz, Nqz, NE, Nw, ncomp, prec, alpha.real, alpha.imag)
+
+
+class Plan:
+    """Owns an sse_plan_t; ``workspace_bytes`` is the device workspace each call needs."""
+
+    def __init__(self, desc, w_shift=None, descs=None, w_shifts=None):
+        self.handle = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        if descs is None:
+            import numpy as np
+            self._shift = np.ascontiguousarray(w_shift, dtype=np.int32)
+            st = lib.sse_plan(ctypes.byref(desc), self._shift.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.byref(self.handle), ctypes.byref(ws))
+            _check(st, "sse_plan")
+            self.n = 1
+            self.descs = [desc]
+        else:
+            import numpy as np
+            n = len(descs)
+            arr = (sse_desc * n)(*descs)
+            self._shifts = [np.ascontiguousarray(s, dtype=np.int32) for s in w_shifts]
+            ptrs = (ctypes.c_void_p * n)(*[s.ctypes.data for s in self._shifts])
+            st = lib.sse_plan_batch(arr, ptrs, n, ctypes.byref(self.handle), ctypes.byref(ws))
+            _check(st, "sse_plan_batch")
+            self.n = n
+            self.descs = list(descs)
+        self.workspace_bytes = ws.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.sse_plan_destroy(h)
+            self.handle = None
+
+
+def sse_plan(desc, w_shift) -> Plan:
+    return Plan(desc, w_shift)
+
+
+def sse_plan_batch(descs, w_shifts) -> Plan:
+    return Plan(None, descs=descs, w_shifts=w_shifts)
+
+
+def sse_compute(plan: Plan, neigh, dH, G, Dt, Sigma, workspace, stream=None, check=True) -> int:
+    st = lib.sse_compute(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt), _ptr(Sigma),
+                         _ptr(workspace), plan.workspace_bytes, _stream(stream))
+    return _check(st, "sse_compute") if check else st
+
+
+def _args(items):
+    arr = (sse_args * len(items))()
+    for t, (neigh, dH, G, Dt, Sigma) in enumerate(items):
+        arr[t] = sse_args(_ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt), _ptr(Sigma))
+    return arr
+
+
+def sse_submit(plan: Plan, items, workspace, stream=None) -> int:
+    """items: one (neigh, dH, G, Dt, Sigma) tuple per instance; returns a ticket."""
+    t = ctypes.c_uint64()
+    arr = _args(items)
+    _check(lib.sse_submit(plan.handle, arr, _ptr(workspace), plan.workspace_bytes,
+                          _stream(stream), ctypes.byref(t)), "sse_submit")
+    return t.value
+
+
+def sse_poll(ticket: int) -> int:
+    st = lib.sse_poll(ticket)
+    if st not in (OK, PENDING):
+        raise SSEError(st, "sse_poll", last_error())
+    return st
+
+
+def sse_wait(ticket: int, check=True) -> int:
+    st = lib.sse_wait(ticket)
+    return _check(st, "sse_wait") if check else st

@@ -1,0 +1,68 @@
+"""Helpers of the GPU parity tests: device inputs from the seeded generator,
+library calls through the C ABI, oracle evaluation on the host and the
+comparison measure (relative Frobenius error)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import ssegen
+from paper_1912_08810_amd import configs
+from ssegen import device_problem as _dp
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def rel_fro(x, y) -> float:
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.linalg.norm((x - y).ravel()) / max(np.linalg.norm(y.ravel()), 1e-300))
+
+
+def max_elem_rel(x, y) -> float:
+    """Largest element-wise deviation, relative to the largest |y| element."""
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+DeviceProblem = _dp.DeviceProblem
+
+
+def oracle_full(dp, comp: int, alpha=1j) -> np.ndarray:
+    """Oracle Sigma of every block of one component of a DeviceProblem."""
+    p = dp.prob
+    dH, D = dp.host_inputs(comp)
+    G = dp._round(ssegen.G(dp.seed, comp, p.Nkz, p.NE, p.NA, p.Norb, scaled=dp.scaled))
+    return oracle.sigma(dp.neigh_h, dH, G, D, p.shifts(), p.Nkz, p.NE, alpha=alpha)
+
+
+def oracle_blocks(dp, comp: int, blocks, alpha=1j) -> np.ndarray:
+    """Oracle Sigma of the listed (k, e, a) blocks; only the G blocks they read
+    are generated on the host."""
+    p = dp.prob
+    dH, D = dp.host_inputs(comp)
+    need = oracle.needed_g_blocks(dp.neigh_h, p.shifts(), p.Nkz, p.Nqz, p.NE, p.NA, blocks)
+    Gb = dp._round(ssegen.G_flat_blocks(dp.seed, comp, p.Norb, need, scaled=dp.scaled))
+    gslot = np.full(p.Nkz * p.NE * p.NA, -1, dtype=np.int64)
+    gslot[need] = np.arange(need.size)
+    return oracle.sigma(dp.neigh_h, dH, Gb, D, p.shifts(), p.Nkz, p.NE, alpha=alpha,
+                        blocks=blocks, gslot=gslot)
+
+
+def sample_blocks(prob: configs.Problem, seed: int, n_e: int = 16, n_a: int = 8):
+    """All k, n_e energies (always including 0, s_max - 1, s_max, NE - 1 and the
+    two ends of an interior tile boundary) and n_a atoms (including 0 and NA - 1)."""
+    rng = np.random.default_rng(seed)
+    s = prob.shifts()
+    smax = int(s.max())
+    es = {0, max(smax - 1, 0), min(smax, prob.NE - 1), prob.NE - 1, prob.NE // 2,
+          prob.NE // 2 - 1}
+    while len(es) < min(n_e, prob.NE):
+        es.add(int(rng.integers(0, prob.NE)))
+    as_ = {0, prob.NA - 1}
+    while len(as_) < min(n_a, prob.NA):
+        as_.add(int(rng.integers(0, prob.NA)))
+    return np.array([(k, e, a) for k in range(prob.Nkz) for e in sorted(es) for a in sorted(as_)],
+                    dtype=np.int32)

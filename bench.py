@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 fp64 FMA lanes/clk x 2
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}  # dense MFMA peak of the operand type
 
 
 def parse():
@@ -31,8 +32,15 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32,bf16x3",
+                    help="precision forms timed after the binary64 headline ('' = none)")
+    ap.add_argument("--only", default="",
+                    help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
     ap.add_argument("--profile-steps", action="store_true",
                     help="print a progress line per step (for profiler runs)")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="after the timed steps, copy a buffer of this many GiB once "
+                         "(reference kernel of known traffic for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -102,35 +110,73 @@ def main():
     prob = configs.DEVICE
     seed = configs.SEED
     ncomp = 2
-    dp = DeviceProblem(prob, seed, ncomp=ncomp)
-    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
-                         ncomp=ncomp, prec=sse.FP64)
-    plan = sse.sse_plan(desc, prob.shifts())
-    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
 
-    def step():
-        sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+    def time_form(prec, fp32, scaled):
+        dp = DeviceProblem(prob, seed, ncomp=ncomp, fp32=fp32, scaled=scaled)
+        desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                             ncomp=ncomp, prec=prec)
+        plan = sse.sse_plan(desc, prob.shifts())
+        ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream()
 
-    for i in range(args.warmup):
-        step()
-        if args.profile_steps:
-            print(f"warmup {i} done", flush=True)
-    torch.cuda.synchronize()
-    times = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        step()
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1) / 1e3)
-        if args.profile_steps:
-            print(f"step {i}: {times[-1]*1e3:.1f} ms", flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+        def step():
+            sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+
+        for i in range(args.warmup):
+            step()
+            if args.profile_steps:
+                print(f"prec {prec} warmup {i} done", flush=True)
+        torch.cuda.synchronize()
+        times = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step()
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+            if args.profile_steps:
+                print(f"prec {prec} step {i}: {times[-1]*1e3:.1f} ms", flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        del dp, ws
+        torch.cuda.empty_cache()
+        return times, wall
+
+    forms = [f for f in args.forms.split(",") if f]
+    if args.only:
+        forms = [args.only] if args.only != "fp64" else []
+    form_out = {}
+    for name in forms:
+        prec = {"fp32": sse.FP32, "bf16x3": sse.BF16X3}[name]
+        ft, _ = time_form(prec, True, True)
+        fm = statistics.median(ft)
+        tf = prob.flops() / (fm / ncomp) / 1e12
+        form_out[name] = {
+            "value": round(prob.flops() * ncomp / fm / 1e9, 1), "unit": "GFLOP/s",
+            "ms_per_step": round(fm * 1e3, 3), "ms_per_step_ci95": round(ci95(ft) * 1e3, 3),
+            "storage": "complex64", "inputs": "G magnitudes spread over ~8 decades",
+            "roofline": {"bound": "mfma", "achieved": round(tf, 3),
+                         "peak": PEAK_MFMA_TFLOPS[name], "unit": "TFLOP/s",
+                         "frac": round(tf / PEAK_MFMA_TFLOPS[name], 4),
+                         "kernel": f"k_sse_mfma<{name}>"},
+            "speedup_vs_fp64": None}
+        print(f"form {name}: {fm*1e3:.1f} ms/step", flush=True)
+    if args.only and args.only != "fp64":
+        print(json.dumps({"forms": form_out}), flush=True)
+        return
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * 2**30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written", flush=True)
+        del src, dst
+    times, wall = time_form(sse.FP64, False, False)
 
     med = statistics.median(times)
     flops_step = prob.flops() * ncomp
@@ -161,7 +207,10 @@ def main():
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
                      "kernel": "k_sse_fp64", "launch_ms": round(t_launch * 1e3, 3)},
+        "forms": form_out,
     }
+    for f in form_out.values():
+        f["speedup_vs_fp64"] = round(med / (f["ms_per_step"] / 1e3), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

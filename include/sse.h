@@ -69,8 +69,10 @@ typedef enum {
     SSE_FP32 = 1,  /* complex64 storage; tap products on fp32 MFMA, fp32 accumulation
                       within one qz row of taps, binary64 accumulation across rows,
                       neighbours and in the dH sandwich */
-    SSE_BF16X3 = 2 /* complex64 storage; tap products as bf16 hi*hi + hi*lo + lo*hi on
-                      MFMA with fp32 accumulation within one qz row, binary64 beyond */
+    SSE_BF16X3 = 2, /* complex64 storage; tap products as bf16 hi*hi + hi*lo + lo*hi on
+                       MFMA with fp32 accumulation within one qz row, binary64 beyond */
+    SSE_FP64C64 = 3 /* complex64 storage, binary64 arithmetic throughout (the fallback
+                       of a complex64 job whose sampled check misses its tolerance) */
 } sse_precision;
 
 typedef struct {
@@ -84,6 +86,9 @@ typedef struct {
     int32_t Nw;    /* phonon frequencies, 1..128 */
     int32_t ncomp; /* 1, or 2 = lesser and greater stacked */
     int32_t prec;  /* sse_precision */
+    int32_t tile_e; /* energies per output tile; 0 = the library's default (the largest
+                       that fills a workgroup); clamped to [1, that default] */
+    int32_t reserved; /* must be 0 */
     double alpha_re, alpha_im; /* prefactor; Eq. (3) is alpha = i (0 + 1i) */
 } sse_desc;
 
@@ -110,11 +115,16 @@ sse_status sse_plan(const sse_desc *desc, const int32_t *w_shift, sse_plan_t *pl
                     size_t *workspace_bytes);
 
 /*
- * Batch plan (persistent launch): n instances of uneven sizes computed by one
- * persistent kernel launch per component.  descs[t] and w_shift[t] as in
- * sse_plan; all instances must share Norb, N3D, ncomp, prec and alpha.
- * Per instance, the tile shape (energies per tile) comes from the plan's
- * size-bucket tuning table (sse_tune_set).
+ * Batch plan (persistent launch): n (1..64) instances of uneven sizes computed
+ * by one persistent kernel launch per component.  descs[t] and w_shift[t] as
+ * in sse_plan; all instances must share Norb, N3D, ncomp, prec and alpha.
+ * Each instance's tile shape is its desc's tile_e (an autotuner picks it per
+ * size bucket).  The launch keeps a fixed grid of two workgroups per compute
+ * unit pulling tiles -- (instance, atom, kz, energy tile) -- from eight work
+ * queues, one per XCD, each holding whole atoms (all kz and energy tiles of an
+ * atom share G rows) ordered by decreasing tile cost; an empty queue's
+ * workgroups take tiles from the others.  Device tables are built at the
+ * first submission.
  */
 sse_status sse_plan_batch(const sse_desc *descs, const int32_t *const *w_shift, int32_t n,
                           sse_plan_t *plan, size_t *workspace_bytes);
@@ -133,6 +143,24 @@ sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, 
  */
 sse_status sse_submit(sse_plan_t plan, const sse_args *args, void *workspace,
                       size_t workspace_bytes, void *stream, uint64_t *ticket);
+
+/*
+ * Sampled binary64 check of a finished complex64 result (a single-instance
+ * plan of precision SSE_FP32, SSE_BF16X3 or SSE_FP64C64, Norb <= 22): the
+ * nblocks output blocks listed in blocks (device int32 [nblocks][3] = k, e, a)
+ * are recomputed in binary64 from the same stored inputs and compared with
+ * args->Sigma.  Enqueued on `stream` behind the work it checks; returns at once
+ * with a ticket.  The ticket finishes with SSE_ERR_TOLERANCE if a component's
+ * relative Frobenius error over the sample exceeds tol, SSE_ERR_ARG if a listed
+ * block is outside the output, else SSE_OK; rel_err (host, ncomp doubles,
+ * caller-owned until the ticket finishes) receives the errors.  The partial
+ * sums are reduced in block order, so the same inputs give the same errors.
+ * Workspace: at least 256 + 16 * nblocks * ncomp bytes, not shared with a
+ * computation in flight.  (The error decides the fallback of a serving job.)
+ */
+sse_status sse_check_submit(sse_plan_t plan, const sse_args *args, const int32_t *blocks,
+                            int32_t nblocks, double tol, double *rel_err, void *workspace,
+                            size_t workspace_bytes, void *stream, uint64_t *ticket);
 
 /* SSE_PENDING while the submission runs, else its final status (the ticket is
  * then released; polling it again gives SSE_ERR_ARG). */

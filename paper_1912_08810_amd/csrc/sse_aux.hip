@@ -11,6 +11,12 @@ namespace {
 
 __global__ void k_clear_status(uint32_t *status) { status[0] = 0u; }
 
+__global__ void k_clear_u64(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n)
+        p[threadIdx.x] = 0ULL;
+}
+
 __global__ void k_validate_neigh(const int32_t *__restrict__ neigh, int64_t n, int32_t NA,
                                  uint32_t *status)
 {
@@ -29,6 +35,12 @@ __global__ void k_validate_neigh(const int32_t *__restrict__ neigh, int64_t n, i
 hipError_t launch_clear_status(uint32_t *status, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
 

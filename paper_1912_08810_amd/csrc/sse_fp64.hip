@@ -56,41 +56,36 @@ __device__ __forceinline__ void cmac(double &accr, double &acci, double dr, doub
     acci = fma(di, gr, acci);
 }
 
-__global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+template <typename T> __device__ __forceinline__ T from_d2(double x, double y);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double x, double y)
 {
-    extern __shared__ double2 lds[];
-    double *ldsA = reinterpret_cast<double *>(lds + p.lds_win);
+    return make_double2(x, y);
+}
+template <> __device__ __forceinline__ float2 from_d2<float2>(double x, double y)
+{
+    return make_float2((float)x, (float)y);
+}
 
-    int64_t L = xcd_remap(blockIdx.x, p.n_wg);
-    const int k = (int)(L % p.Nkz);
-    L /= p.Nkz;
-    const int et = (int)(L % p.n_etiles);
-    const int a = (int)(L / p.n_etiles);
+// One output tile: energies [et TE, et TE + TE) of (k, a).  p supplies the
+// problem's sizes and tap table (it may live in global memory), ptr its tensors.
+// T is the storage type of G, D~ and Sigma (complex128, or complex64 promoted to
+// binary64 on load); all arithmetic is binary64.
+template <typename T>
+__device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs &ptr, int a, int k,
+                                          int et, double2 *lds)
+{
+    double *ldsA = reinterpret_cast<double *>(lds + p.lds_win);
     const int e0 = et * p.TE;
     const int te = min(p.TE, p.NE - e0);
     const int NN = p.NN, No = p.Norb;
     const int P = te * NN;
     const int Pst = p.TE * NN;  // scratch stride between the three filters of a round
     const int tid = threadIdx.x;
-
-    int pos[kR];
-    bool valid[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        pos[r] = tid + r * kBlock;
-        valid[r] = pos[r] < P;
-        if (!valid[r])
-            pos[r] = 0;
-    }
-    // orbital coordinates of each position: energy el, row m, column n
-    int pe[kR], pm[kR], pn[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        pe[r] = pos[r] / NN;
-        const int c = pos[r] - pe[r] * NN;
-        pm[r] = c / No;
-        pn[r] = c - pm[r] * No;
-    }
+    // Thread tid owns positions tid + 256 r.  Positions at or beyond P are
+    // computed from in-bounds LDS (the window region is padded to 1024 +
+    // spread) and never stored.
 
     double sr[kR], si[kR];
 #pragma unroll
@@ -101,9 +96,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
 
     const size_t strideD = (size_t)p.NA * p.NB * kNF;  // one (q, w) slab of D~
     const size_t strideE = (size_t)p.NA * NN;          // one energy row of G
+    // staging walk: element idx = tid + 256 it is (energy ew, channel cc)
+    const int st_e = kBlock / NN, st_c = kBlock - (kBlock / NN) * NN;
+    const int ew0 = tid / NN, cc0 = tid - (tid / NN) * NN;
 
     for (int b = 0; b < p.NB; ++b) {
-        const int f = p.neigh[(size_t)a * p.NB + b];
+        const int f = ptr.neigh[(size_t)a * p.NB + b];
         if ((unsigned)f >= (unsigned)p.NA)
             continue;  // invalid neighbour: reported by the validation kernel
 
@@ -116,44 +114,77 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
                 ai[r][x] = 0.0;
             }
 
-        const double2 *Dab = p.D + ((size_t)a * p.NB + b) * kNF;
+        const T *Dab = (const T *)ptr.D + ((size_t)a * p.NB + b) * kNF;
         for (int q = 0; q < p.Nqz; ++q) {
             int kk = k - q;
             if (kk < 0)
                 kk += p.Nkz;
-            const double2 *Gk = p.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
+            const T *Gk = (const T *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
+            const T *Dq = Dab + (size_t)q * p.Nw * strideD;
             for (int c = 0; c < p.taps.nchunk; ++c) {
                 const int t0 = p.taps.cb[c], t1 = p.taps.cb[c + 1];
                 const int smax = p.taps.s[t0], smin = p.taps.s[t1 - 1];
                 const int wn = (te + smax - smin) * NN;
                 const int ebase = e0 - smax;
                 __syncthreads();
-                for (int idx = tid; idx < wn; idx += kBlock) {
-                    const int ew = idx / NN;
-                    const int cc = idx - ew * NN;
-                    const int e = ebase + ew;
-                    double2 v = make_double2(0.0, 0.0);
-                    if (e >= 0 && e < p.NE)
-                        v = Gk[(size_t)e * strideE + cc];
-                    lds[idx] = v;
+                {
+                    int ew = ew0, cc = cc0;
+                    for (int idx = tid; idx < wn; idx += kBlock) {
+                        const int e = ebase + ew;
+                        double2 v = make_double2(0.0, 0.0);
+                        if (e >= 0 && e < p.NE)
+                            v = to_d2(Gk[(size_t)e * strideE + cc]);
+                        lds[idx] = v;
+                        cc += st_c;
+                        ew += st_e;
+                        if (cc >= NN) {
+                            cc -= NN;
+                            ++ew;
+                        }
+                    }
                 }
                 __syncthreads();
-                for (int t = t0; t < t1; ++t) {
-                    const int off = (smax - p.taps.s[t]) * NN;
-                    const double2 *dp = Dab + (size_t)(q * p.Nw + p.taps.w[t]) * strideD;
-                    double dr[kNF], di[kNF];
+                // Taps in pairs: both taps' D~ values (scalar loads) and window
+                // reads are issued before one wait, then 2 x 36 FMAs per position.
+                // (complex64 storage keeps single taps: its conversions need the registers)
+                int t = t0;
+                constexpr int kPair = sizeof(T) == sizeof(double2) ? 1 : 0;
+                for (; kPair && t + 1 < t1; t += 2) {
+                    const T *dpa = Dq + (size_t)p.taps.w[t] * strideD;
+                    const T *dpb = Dq + (size_t)p.taps.w[t + 1] * strideD;
+                    double2 da[kNF], db[kNF];
 #pragma unroll
                     for (int x = 0; x < kNF; ++x) {
-                        const double2 d = dp[x];
-                        dr[x] = d.x;
-                        di[x] = d.y;
+                        da[x] = to_d2(dpa[x]);
+                        db[x] = to_d2(dpb[x]);
                     }
+                    const double2 *wpa = lds + tid + (smax - p.taps.s[t]) * NN;
+                    const double2 *wpb = lds + tid + (smax - p.taps.s[t + 1]) * NN;
 #pragma unroll
                     for (int r = 0; r < kR; ++r) {
-                        const double2 g = lds[pos[r] + off];
+                        const double2 ga = wpa[r * kBlock];
+                        const double2 gb = wpb[r * kBlock];
 #pragma unroll
                         for (int x = 0; x < kNF; ++x)
-                            cmac(ar[r][x], ai[r][x], dr[x], di[x], g.x, g.y);
+                            cmac(ar[r][x], ai[r][x], da[x].x, da[x].y, ga.x, ga.y);
+#pragma unroll
+                        for (int x = 0; x < kNF; ++x)
+                            cmac(ar[r][x], ai[r][x], db[x].x, db[x].y, gb.x, gb.y);
+                    }
+                }
+                for (; t < t1; ++t) {
+                    const T *dpa = Dq + (size_t)p.taps.w[t] * strideD;
+                    double2 da[kNF];
+#pragma unroll
+                    for (int x = 0; x < kNF; ++x)
+                        da[x] = to_d2(dpa[x]);
+                    const double2 *wpa = lds + tid + (smax - p.taps.s[t]) * NN;
+#pragma unroll
+                    for (int r = 0; r < kR; ++r) {
+                        const double2 ga = wpa[r * kBlock];
+#pragma unroll
+                        for (int x = 0; x < kNF; ++x)
+                            cmac(ar[r][x], ai[r][x], da[x].x, da[x].y, ga.x, ga.y);
                     }
                 }
             }
@@ -161,7 +192,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
 
         // ---- sandwich: Sigma += sum_ij dH_i Gh_ij dH_j^T for this neighbour
         __syncthreads();  // window reads done; LDS becomes scratch
-        const double *Ag = p.dH + ((size_t)a * p.NB + b) * kN3D * NN;
+        const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
         for (int idx = tid; idx < kN3D * NN; idx += kBlock)
             ldsA[idx] = Ag[idx];
 
@@ -180,15 +211,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
                 __syncthreads();
 #pragma unroll
             for (int r = 0; r < kR; ++r)
-                if (valid[r])
+                if (tid + r * kBlock < P)
 #pragma unroll
                     for (int j = 0; j < kN3D; ++j)
-                        lds[j * Pst + pos[r]] = make_double2(ar[r][i * kN3D + j], ai[r][i * kN3D + j]);
+                        lds[j * Pst + tid + r * kBlock] =
+                            make_double2(ar[r][i * kN3D + j], ai[r][i * kN3D + j]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                const int base = pe[r] * NN + pn[r];
-                const double *Arow = ldsA + i * NN + pm[r] * No;
+                const int pos = tid + r * kBlock < P ? tid + r * kBlock : 0;
+                const int el = pos / NN, cpos = pos - el * NN;
+                const int m = cpos / No, n = cpos - m * No;
+                const int base = el * NN + n;
+                const double *Arow = ldsA + i * NN + m * No;
                 for (int l = 0; l < No; ++l) {
                     const double am = Arow[l];
 #pragma unroll
@@ -203,18 +238,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kR; ++r)
-            if (valid[r])
+            if (tid + r * kBlock < P)
 #pragma unroll
                 for (int j = 0; j < kN3D; ++j)
-                    lds[j * Pst + pos[r]] = make_double2(tr[r][j], ti[r][j]);
+                    lds[j * Pst + tid + r * kBlock] = make_double2(tr[r][j], ti[r][j]);
         __syncthreads();
         // Sigma_mn += sum_j sum_l T_j[m, l] dH_j[n, l]
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const int base = pe[r] * NN + pm[r] * No;
+            const int pos = tid + r * kBlock < P ? tid + r * kBlock : 0;
+            const int el = pos / NN, cpos = pos - el * NN;
+            const int m = cpos / No, n = cpos - m * No;
+            const int base = el * NN + m * No;
 #pragma unroll
             for (int j = 0; j < kN3D; ++j) {
-                const double *Arow = ldsA + j * NN + pn[r] * No;
+                const double *Arow = ldsA + j * NN + n * No;
                 for (int l = 0; l < No; ++l) {
                     const double2 s = lds[j * Pst + base + l];
                     const double am = Arow[l];
@@ -226,14 +264,53 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
     }
 
     // ---- Sigma[k, e0 + el, a] = alpha * accumulated sum
-    double2 *Sk = p.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
+    T *Sk = (T *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-        if (!valid[r])
+        const int pos = tid + r * kBlock;
+        if (pos >= P)
             continue;
-        const int c = pos[r] - pe[r] * NN;
-        Sk[(size_t)pe[r] * strideE + c] =
-            make_double2(p.alpha_re * sr[r] - p.alpha_im * si[r], p.alpha_re * si[r] + p.alpha_im * sr[r]);
+        const int el = pos / NN;
+        const int c = pos - el * NN;
+        Sk[(size_t)el * strideE + c] = from_d2<T>(p.alpha_re * sr[r] - p.alpha_im * si[r],
+                                                 p.alpha_re * si[r] + p.alpha_im * sr[r]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
+{
+    extern __shared__ double2 lds[];
+    int64_t L = xcd_remap(blockIdx.x, p.n_wg);
+    const int k = (int)(L % p.Nkz);
+    L /= p.Nkz;
+    const int et = (int)(L % p.n_etiles);
+    const int a = (int)(L / p.n_etiles);
+    const TensorPtrs ptr{p.neigh, p.dH, p.G, p.D, p.Sigma};
+    fp64_tile<T>(p, ptr, a, k, et, lds);
+}
+
+// Persistent form: a fixed grid pulls tiles from the batch's work queues
+// (one queue per XCD, then the others) until all are taken.
+template <typename T>
+__global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLaunch bl)
+{
+    extern __shared__ double2 lds[];
+    __shared__ int s_tile[4];
+    const int home = blockIdx.x & 7;
+    for (;;) {
+        if (threadIdx.x == 0)
+            batch_pull(bl, home, s_tile);
+        __syncthreads();
+        const int inst = __builtin_amdgcn_readfirstlane(s_tile[0]);
+        const int a = __builtin_amdgcn_readfirstlane(s_tile[1]);
+        const int k = __builtin_amdgcn_readfirstlane(s_tile[2]);
+        const int et = __builtin_amdgcn_readfirstlane(s_tile[3]);
+        __syncthreads();
+        if (inst < 0)
+            break;
+        const Fp64Params &p = reinterpret_cast<const Fp64Params *>(bl.params)[inst];
+        fp64_tile<T>(p, bl.ptr[inst], a, k, et, lds);
     }
 }
 
@@ -255,10 +332,10 @@ TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     long win_max = 0;
     while (t < taps.n) {
         int u = t + 1;
-        while (u < taps.n && (long)(TE + taps.s[t] - taps.s[u]) * NN <= budget)
+        while (u < taps.n && kPmax + (long)(taps.s[t] - taps.s[u]) * NN <= budget)
             ++u;
         out->cb[out->nchunk++] = t;
-        win_max = std::max(win_max, (long)(TE + taps.s[t] - taps.s[u - 1]) * NN);
+        win_max = std::max(win_max, kPmax + (long)(taps.s[t] - taps.s[u - 1]) * NN);
         t = u;
     }
     out->cb[out->nchunk] = taps.n;
@@ -270,22 +347,48 @@ TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     return g;
 }
 
-hipError_t fp64_launch(const Fp64Params &p, size_t lds_bytes, hipStream_t s)
+template <typename K>
+static hipError_t set_lds_attr(K kernel, bool &done)
+{
+    if (done)
+        return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kLdsBudget + 4096));
+    done = e == hipSuccess;
+    return e;
+}
+
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, size_t lds_bytes,
+                                  hipStream_t s)
+{
+    static bool done[2] = {false, false};
+    hipError_t e = c64 ? set_lds_attr(k_sse_fp64_persistent<float2>, done[1])
+                       : set_lds_attr(k_sse_fp64_persistent<double2>, done[0]);
+    if (e != hipSuccess)
+        return e;
+    if (c64)
+        hipLaunchKernelGGL(k_sse_fp64_persistent<float2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
+    else
+        hipLaunchKernelGGL(k_sse_fp64_persistent<double2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
+    return hipGetLastError();
+}
+
+hipError_t fp64_launch(const Fp64Params &p, bool c64, size_t lds_bytes, hipStream_t s)
 {
     if (p.n_wg <= 0)
         return hipSuccess;
     if (p.n_wg > 0x7fffffffLL)
         return hipErrorInvalidConfiguration;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_sse_fp64,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kLdsBudget + 4096));
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_sse_fp64, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
+    static bool done[2] = {false, false};
+    hipError_t e = c64 ? set_lds_attr(k_sse_fp64<float2>, done[1])
+                       : set_lds_attr(k_sse_fp64<double2>, done[0]);
+    if (e != hipSuccess)
+        return e;
+    if (c64)
+        hipLaunchKernelGGL(k_sse_fp64<float2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
+    else
+        hipLaunchKernelGGL(k_sse_fp64<double2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
     return hipGetLastError();
 }
 

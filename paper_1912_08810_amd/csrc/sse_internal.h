@@ -26,13 +26,77 @@ struct TapTable {
     int32_t cb[kMaxTaps + 1];
 };
 
-// Launch parameters of the FP64 tiled kernel (one component).
+// Device pointers of one instance (one component); aux is the MFMA path's
+// A-fragment buffer.
+struct TensorPtrs {
+    const int32_t *neigh;
+    const double *dH;
+    const void *G;
+    const void *D;
+    void *Sigma;
+    const void *aux;
+};
+
+constexpr int kMaxBatch = 64;
+constexpr int kQueues = 8;  // one work queue per XCD
+
+// Kernel argument of a persistent batched launch.  Tiles are grouped in atom
+// chunks (all (k, energy-tile) tiles of one atom of one instance); chunk j of
+// queue x is chunk_inst/chunk_atom[j] for j in [qbeg[x], qbeg[x+1]) and its
+// tiles have queue-local indices [chunk_start[j], chunk_start[j + 1]).
+struct BatchLaunch {
+    const void *params;            // per-instance Fp64Params / MfmaParams (sizes, taps)
+    const int32_t *chunk_inst;
+    const int32_t *chunk_atom;
+    const int64_t *chunk_start;
+    unsigned long long *counters;  // kQueues pull counters (workspace, cleared per launch)
+    int32_t qbeg[kQueues + 1];
+    int64_t qcount[kQueues];
+    int32_t nkz[kMaxBatch];
+    TensorPtrs ptr[kMaxBatch];
+};
+
+// Thread 0 of a workgroup takes the next tile: its home queue first, then the
+// others.  s_tile = (instance, atom, k, energy tile), instance -1 when all
+// queues are empty.
+__device__ __forceinline__ void batch_pull(const BatchLaunch &bl, int home, int *s_tile)
+{
+    for (int d = 0; d < kQueues; ++d) {
+        const int qx = (home + d) & (kQueues - 1);
+        if (bl.qcount[qx] == 0)
+            continue;
+        const long long t = (long long)atomicAdd(&bl.counters[qx], 1ULL);
+        if (t >= bl.qcount[qx])
+            continue;
+        int lo = bl.qbeg[qx], hi = bl.qbeg[qx + 1] - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bl.chunk_start[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = bl.chunk_inst[lo];
+        const long long rem = t - bl.chunk_start[lo];
+        const int nkz = bl.nkz[inst];
+        s_tile[0] = inst;
+        s_tile[1] = bl.chunk_atom[lo];
+        s_tile[2] = (int)(rem % nkz);
+        s_tile[3] = (int)(rem / nkz);
+        return;
+    }
+    s_tile[0] = -1;
+    s_tile[1] = s_tile[2] = s_tile[3] = 0;
+}
+
+// Launch parameters of the FP64 tiled kernel (one component).  G, D and Sigma
+// are complex128, or complex64 for SSE_FP64C64.
 struct Fp64Params {
     const int32_t *neigh;
     const double *dH;
-    const double2 *G;
-    const double2 *D;
-    double2 *Sigma;
+    const void *G;
+    const void *D;
+    void *Sigma;
     int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
     int32_t TE;        // energies per tile
     int32_t n_etiles;  // ceil(NE / TE)
@@ -42,24 +106,89 @@ struct Fp64Params {
     TapTable taps;
 };
 
+// Groups of eight consecutive taps of one chunk (the K extent of one MFMA
+// step); taps past the chunk's end are padding with zero weight.
+struct GroupTable {
+    int32_t n;                    // groups per qz row
+    int32_t gb[kMaxTaps + 1];     // groups of chunk c are [gb[c], gb[c+1])
+    int32_t t0[kMaxTaps];         // first tap of group g
+};
+
+// Launch parameters of the MFMA (complex64-storage) kernel, one component.
+struct MfmaParams {
+    const int32_t *neigh;
+    const double *dH;
+    const float2 *G;
+    const void *afrag;  // per (a, b, q, group, lane) A-operand fragments (prep kernel)
+    float2 *Sigma;
+    int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
+    int32_t TE, n_etiles;
+    int64_t n_wg;
+    int32_t lds_win;   // 8-byte elements of the window region
+    int32_t lds_scr;   // complex128 elements of the sandwich scratch region
+    double alpha_re, alpha_im;
+    TapTable taps;
+    GroupTable groups;
+};
+
+struct MfmaPrepParams {
+    const float2 *D;
+    void *afrag;
+    int32_t NA, NB, Nqz, Nw;
+    TapTable taps;
+    GroupTable groups;
+};
+
+// Sampled binary64 check of a complex64 result (sse_check.hip).
+struct CheckParams {
+    const int32_t *neigh;
+    const double *dH;
+    const float2 *G;
+    const float2 *D;
+    const float2 *Sigma;
+    const int32_t *blocks;  // [nblocks][3] = (k, e, a)
+    int32_t nblocks;
+    double *partial;        // [nblocks][2] workspace
+    uint32_t *status;
+    int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
+    double alpha_re, alpha_im;
+    int32_t shift[kMaxTaps];  // energy shift of frequency w
+};
+
 // Tile geometry for one problem: energies per tile, window size, LDS bytes.
 struct TileGeom {
     int TE;
     int n_etiles;
-    int lds_win;     // complex128 elements of the window/scratch region
+    int lds_win;     // window elements (complex128 for fp64, 8-byte for the MFMA path)
+    int lds_scr;     // complex128 elements of the sandwich scratch (MFMA path)
     size_t lds_bytes;
 };
 
 // Host helpers (sse_fp64.hip).
 TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
                        TapTable *taps_out);
-hipError_t fp64_launch(const Fp64Params &p, size_t lds_bytes, hipStream_t s);
+hipError_t fp64_launch(const Fp64Params &p, bool c64, size_t lds_bytes, hipStream_t s);
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, size_t lds_bytes,
+                                  hipStream_t s);
+
+// MFMA path (sse_mfma.hip).  prec is SSE_FP32 or SSE_BF16X3.
+TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
+                       TapTable *taps_out, GroupTable *groups_out);
+size_t mfma_afrag_bytes(int prec, int NA, int NB, int Nqz, const GroupTable &g);
+hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s);
+hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStream_t s);
+hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,
+                                  hipStream_t s);
 
 // Auxiliary kernels (sse_aux.hip).
 hipError_t launch_clear_status(uint32_t *status, hipStream_t s);
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_validate_neigh(const int32_t *neigh, int64_t n, int32_t NA, uint32_t *status,
                                  hipStream_t s);
 
 constexpr uint32_t kStatusBadNeigh = 1u;
+constexpr uint32_t kStatusBadBlock = 2u;
+
+hipError_t check_launch(const CheckParams &p, double *out, hipStream_t s);
 
 }  // namespace sse

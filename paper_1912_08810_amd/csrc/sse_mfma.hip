@@ -1,0 +1,505 @@
+// sse_mfma.hip -- complex64-storage scattering self-energy on the gfx950
+// matrix cores: the (qz, w) tap filters of Eq. (3) (Sec. 2) as a GEMM on
+// MFMA, the dH sandwich in binary64.
+//
+// For one bond (a, b) with neighbour f, the tap sum
+//   Gh_ij[k, e, c] = sum_{q, w} Dt[q, w, a, b, i, j] G[(k - q) mod Nkz, e - s_w, f, c]
+// is a real GEMM  C[row, pos] = sum_K A[row, K] B[K, pos]  with
+//   row = 2 ij + (re | im)                         (18 of the 32 MFMA rows),
+//   K   = 2 tap + (re | im)                         (the complex product written out),
+//   pos = (energy, orbital pair) of the output tile (32 MFMA columns per tile),
+//   A[(ij, re), (t, re)] = Re D, A[(ij, re), (t, im)] = -Im D,
+//   A[(ij, im), (t, re)] = Im D, A[(ij, im), (t, im)] =  Re D,
+//   B[(t, x), pos] = component x of G at the tap-shifted window position.
+// B is read straight from the LDS window of the neighbour's G rows (a tap is a
+// uniform offset, so the im2col matrix is never formed); A depends only on
+// (a, b, q) and is pre-arranged per lane by k_prep_afrag.
+//
+// SSE_FP32:   v_mfma_f32_32x32x2_f32, one tap per instruction.
+// SSE_BF16X3: v_mfma_f32_32x32x16_bf16, eight taps per instruction; every fp32
+//             operand x is split x = hi + lo (bf16 hi, bf16 lo = x - hi) and the
+//             product is hi*hi + hi*lo + lo*hi.
+// Accumulation: fp32 inside the MFMA over the taps of one energy window (one
+// qz row), binary64 across qz rows, neighbours and in the sandwich.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sse_internal.h"
+
+namespace sse {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kNT = 4;                      // 32-column tiles per wave
+constexpr int kPwg = kWaves * kNT * 32;     // output positions per workgroup
+constexpr int kGS = 8;                      // taps per group
+constexpr size_t kWinBudget = 64 * 1024;    // LDS bytes for the G window
+constexpr int kSR = kPwg / kBlock;          // sandwich positions per thread
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
+{
+    const int64_t per = n >> 3;
+    if (bid >= (per << 3))
+        return bid;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    __bf16 h = (__bf16)x;
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
+__device__ __forceinline__ float bf16_value(uint32_t bits)
+{
+    return __builtin_bit_cast(float, bits << 16);
+}
+
+// hi and lo bf16 parts of x packed as (hi, lo) bit patterns.
+__device__ __forceinline__ void split_bf16(float x, uint32_t &hi, uint32_t &lo)
+{
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+}
+
+// A-operand value of MFMA row r for tap t, K component x (0 = re, 1 = im).
+__device__ __forceinline__ float a_value(const MfmaPrepParams &p, int ab, int q, int row, int t,
+                                         int tend, int x)
+{
+    const int ij = row >> 1, ri = row & 1;
+    if (ij >= kNF || t >= tend)
+        return 0.0f;
+    const float2 d = p.D[(((size_t)q * p.Nw + p.taps.w[t]) * p.NA * p.NB + ab) * kNF + ij];
+    if (ri == 0)
+        return x == 0 ? d.x : -d.y;
+    return x == 0 ? d.y : d.x;
+}
+
+// One thread per (a, b, q, group, lane): the lane's 32-byte A fragment.
+template <int PREC>
+__global__ void k_prep_afrag(const MfmaPrepParams p)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = (int)(idx & 63);
+    int64_t rest = idx >> 6;
+    const int g = (int)(rest % p.groups.n);
+    rest /= p.groups.n;
+    const int q = (int)(rest % p.Nqz);
+    const int64_t ab = rest / p.Nqz;
+    if (ab >= (int64_t)p.NA * p.NB)
+        return;
+    int c = 0;
+    while (p.groups.gb[c + 1] <= g)
+        ++c;
+    const int tend = p.taps.cb[c + 1];
+    const int t0 = p.groups.t0[g];
+    const int row = lane & 31, h = lane >> 5;
+    uint4 *out = reinterpret_cast<uint4 *>(p.afrag) + (idx << 1);
+    if (PREC == SSE_BF16X3) {
+        uint32_t hi[8], lo[8];
+        for (int u = 0; u < 4; ++u)
+            for (int x = 0; x < 2; ++x)
+                split_bf16(a_value(p, (int)ab, q, row, t0 + 4 * h + u, tend, x), hi[2 * u + x],
+                           lo[2 * u + x]);
+        out[0] = make_uint4(hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16,
+                            hi[6] | hi[7] << 16);
+        out[1] = make_uint4(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16,
+                            lo[6] | lo[7] << 16);
+    } else {
+        float v[8];
+        for (int u = 0; u < 8; ++u)
+            v[u] = a_value(p, (int)ab, q, row, t0 + u, tend, h);
+        out[0] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                            __float_as_uint(v[3]));
+        out[1] = make_uint4(__float_as_uint(v[4]), __float_as_uint(v[5]), __float_as_uint(v[6]),
+                            __float_as_uint(v[7]));
+    }
+}
+
+// One output tile (energies [et TE, et TE + TE) of (k, a)); p supplies sizes and
+// tap/group tables (possibly from global memory), ptr the tensors (aux = A fragments).
+template <int PREC>
+__device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs &ptr, int a, int k,
+                                          int et, unsigned char *smem)
+{
+    uint2 *win = reinterpret_cast<uint2 *>(smem);       // G window, 8 bytes per complex
+    double2 *scr = reinterpret_cast<double2 *>(smem);   // sandwich scratch (aliases window)
+    const size_t a_off = ((size_t)p.lds_win * 8 > (size_t)p.lds_scr * 16) ? (size_t)p.lds_win * 8
+                                                                          : (size_t)p.lds_scr * 16;
+    double *ldsA = reinterpret_cast<double *>(smem + a_off);
+
+    const int e0 = et * p.TE;
+    const int te = min(p.TE, p.NE - e0);
+    const int NN = p.NN, No = p.Norb;
+    const int P = te * NN;
+    const int Pst = p.TE * NN;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+
+    // MFMA columns of this lane: one output position per tile
+    int pcol[kNT];
+    bool pval[kNT];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+        pcol[t] = (wave * kNT + t) * 32 + (lane & 31);
+        pval[t] = pcol[t] < P;
+        if (!pval[t])
+            pcol[t] = 0;
+    }
+    // sandwich positions of this thread
+    int spos[kSR], pe[kSR], pm[kSR], pn[kSR];
+    bool sval[kSR];
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+        spos[r] = tid + r * kBlock;
+        sval[r] = spos[r] < P;
+        if (!sval[r])
+            spos[r] = 0;
+        pe[r] = spos[r] / NN;
+        const int c = spos[r] - pe[r] * NN;
+        pm[r] = c / No;
+        pn[r] = c - pm[r] * No;
+    }
+    double sr[kSR], si[kSR];
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+        sr[r] = 0.0;
+        si[r] = 0.0;
+    }
+
+    const size_t strideE = (size_t)p.NA * NN;
+    const uint4 *afrag = reinterpret_cast<const uint4 *>(ptr.aux);
+
+    for (int b = 0; b < p.NB; ++b) {
+        const int f = ptr.neigh[(size_t)a * p.NB + b];
+        if ((unsigned)f >= (unsigned)p.NA)
+            continue;
+        double acc[kNT][10];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int v = 0; v < 10; ++v)
+                acc[t][v] = 0.0;
+
+        for (int q = 0; q < p.Nqz; ++q) {
+            int kk = k - q;
+            if (kk < 0)
+                kk += p.Nkz;
+            const float2 *Gk =
+                (const float2 *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
+            const uint4 *aq = afrag + ((((size_t)a * p.NB + b) * p.Nqz + q) * p.groups.n) * 128;
+            for (int c = 0; c < p.taps.nchunk; ++c) {
+                const int t1c = p.taps.cb[c + 1];
+                const int smax = p.taps.s[p.taps.cb[c]], smin = p.taps.s[t1c - 1];
+                const int wn = (te + smax - smin) * NN;
+                const int ebase = e0 - smax;
+                __syncthreads();
+                for (int idx = tid; idx < wn; idx += kBlock) {
+                    const int ew = idx / NN;
+                    const int cc = idx - ew * NN;
+                    const int e = ebase + ew;
+                    float2 v = make_float2(0.0f, 0.0f);
+                    if (e >= 0 && e < p.NE)
+                        v = Gk[(size_t)e * strideE + cc];
+                    uint2 w;
+                    if (PREC == SSE_BF16X3) {
+                        uint32_t rh, rl, ih, il;
+                        split_bf16(v.x, rh, rl);
+                        split_bf16(v.y, ih, il);
+                        w = make_uint2(rh | ih << 16, rl | il << 16);
+                    } else {
+                        w = make_uint2(__float_as_uint(v.x), __float_as_uint(v.y));
+                    }
+                    win[idx] = w;
+                }
+                __syncthreads();
+
+                f32x16 C[kNT];
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        C[t][v] = 0.0f;
+
+                for (int g = p.groups.gb[c]; g < p.groups.gb[c + 1]; ++g) {
+                    const uint4 A0 = aq[(size_t)g * 128 + lane * 2];
+                    const uint4 A1 = aq[(size_t)g * 128 + lane * 2 + 1];
+                    const int tg = p.groups.t0[g];
+                    if (PREC == SSE_BF16X3) {
+                        int off[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int t = tg + 4 * h + u;
+                            off[u] = t < t1c ? (smax - p.taps.s[t]) * NN : 0;
+                        }
+                        const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
+                        const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
+#pragma unroll
+                        for (int t = 0; t < kNT; ++t) {
+                            uint2 w[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                w[u] = win[pcol[t] + off[u]];
+                            const bf16x8 bhi =
+                                __builtin_bit_cast(bf16x8, make_uint4(w[0].x, w[1].x, w[2].x, w[3].x));
+                            const bf16x8 blo =
+                                __builtin_bit_cast(bf16x8, make_uint4(w[0].y, w[1].y, w[2].y, w[3].y));
+                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0, 0);
+                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, C[t], 0, 0, 0);
+                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, C[t], 0, 0, 0);
+                        }
+                    } else {
+                        const float av[8] = {__uint_as_float(A0.x), __uint_as_float(A0.y),
+                                             __uint_as_float(A0.z), __uint_as_float(A0.w),
+                                             __uint_as_float(A1.x), __uint_as_float(A1.y),
+                                             __uint_as_float(A1.z), __uint_as_float(A1.w)};
+                        const float *winf = reinterpret_cast<const float *>(win);
+#pragma unroll
+                        for (int u = 0; u < kGS; ++u) {
+                            const int t = tg + u;
+                            const int off = t < t1c ? (smax - p.taps.s[t]) * NN : 0;
+#pragma unroll
+                            for (int tt = 0; tt < kNT; ++tt) {
+                                const float bv = winf[2 * (pcol[tt] + off) + h];
+                                C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, C[tt], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+                // fold this window's fp32 partial sums into the binary64 accumulators
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 10; ++v)
+                        acc[t][v] += (double)C[t][v];
+            }
+        }
+
+        // ---- binary64 sandwich: Sigma += sum_ij dH_i Gh_ij dH_j^T
+        __syncthreads();
+        const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
+        for (int idx = tid; idx < kN3D * NN; idx += kBlock)
+            ldsA[idx] = Ag[idx];
+        double tr[kSR][kN3D], ti[kSR][kN3D];
+#pragma unroll
+        for (int r = 0; r < kSR; ++r)
+#pragma unroll
+            for (int j = 0; j < kN3D; ++j) {
+                tr[r][j] = 0.0;
+                ti[r][j] = 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < kN3D; ++i) {
+            if (i > 0)
+                __syncthreads();
+            // C rows held by this lane: row = 8 (v / 4) + 4 h + v % 4, row = 2 ij + re/im
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int v = 0; v < 10; v += 2) {
+                    const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int ij = row >> 1;
+                    if (ij < kNF && ij / kN3D == i && pval[t])
+                        scr[(ij % kN3D) * Pst + pcol[t]] = make_double2(acc[t][v], acc[t][v + 1]);
+                }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kSR; ++r) {
+                const int base = pe[r] * NN + pn[r];
+                const double *Arow = ldsA + i * NN + pm[r] * No;
+                for (int l = 0; l < No; ++l) {
+                    const double am = Arow[l];
+#pragma unroll
+                    for (int j = 0; j < kN3D; ++j) {
+                        const double2 s = scr[j * Pst + base + l * No];
+                        tr[r][j] = fma(am, s.x, tr[r][j]);
+                        ti[r][j] = fma(am, s.y, ti[r][j]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSR; ++r)
+            if (sval[r])
+#pragma unroll
+                for (int j = 0; j < kN3D; ++j)
+                    scr[j * Pst + spos[r]] = make_double2(tr[r][j], ti[r][j]);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSR; ++r) {
+            const int base = pe[r] * NN + pm[r] * No;
+#pragma unroll
+            for (int j = 0; j < kN3D; ++j) {
+                const double *Arow = ldsA + j * NN + pn[r] * No;
+                for (int l = 0; l < No; ++l) {
+                    const double2 s = scr[j * Pst + base + l];
+                    const double am = Arow[l];
+                    sr[r] = fma(s.x, am, sr[r]);
+                    si[r] = fma(s.y, am, si[r]);
+                }
+            }
+        }
+    }
+
+    float2 *Sk = (float2 *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+        if (!sval[r])
+            continue;
+        const int c = spos[r] - pe[r] * NN;
+        Sk[(size_t)pe[r] * strideE + c] =
+            make_float2((float)(p.alpha_re * sr[r] - p.alpha_im * si[r]),
+                        (float)(p.alpha_re * si[r] + p.alpha_im * sr[r]));
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t L = xcd_remap(blockIdx.x, p.n_wg);
+    const int k = (int)(L % p.Nkz);
+    L /= p.Nkz;
+    const int et = (int)(L % p.n_etiles);
+    const int a = (int)(L / p.n_etiles);
+    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
+    mfma_tile<PREC>(p, ptr, a, k, et, smem);
+}
+
+// Persistent form over a batch's work queues (see batch_pull).
+template <int PREC>
+__global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLaunch bl)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_tile[4];
+    const int home = blockIdx.x & 7;
+    for (;;) {
+        if (threadIdx.x == 0)
+            batch_pull(bl, home, s_tile);
+        __syncthreads();
+        const int inst = __builtin_amdgcn_readfirstlane(s_tile[0]);
+        const int a = __builtin_amdgcn_readfirstlane(s_tile[1]);
+        const int k = __builtin_amdgcn_readfirstlane(s_tile[2]);
+        const int et = __builtin_amdgcn_readfirstlane(s_tile[3]);
+        __syncthreads();
+        if (inst < 0)
+            break;
+        const MfmaParams &p = reinterpret_cast<const MfmaParams *>(bl.params)[inst];
+        mfma_tile<PREC>(p, bl.ptr[inst], a, k, et, smem);
+    }
+}
+
+}  // namespace
+
+TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out,
+                       GroupTable *groups)
+{
+    const int NN = Norb * Norb;
+    int TE = kPwg / NN;
+    if (te_request > 0)
+        TE = std::min(TE, te_request);
+    TE = std::max(1, std::min(TE, NE));
+    const long budget = (long)(kWinBudget / 8);
+    *out = taps;
+    out->nchunk = 0;
+    groups->n = 0;
+    int t = 0;
+    long win_max = 0;
+    while (t < taps.n) {
+        int u = t + 1;
+        while (u < taps.n && (long)(TE + taps.s[t] - taps.s[u]) * NN <= budget)
+            ++u;
+        groups->gb[out->nchunk] = groups->n;
+        for (int g = t; g < u; g += kGS)
+            groups->t0[groups->n++] = g;
+        out->cb[out->nchunk++] = t;
+        win_max = std::max(win_max, (long)(TE + taps.s[t] - taps.s[u - 1]) * NN);
+        t = u;
+    }
+    out->cb[out->nchunk] = taps.n;
+    groups->gb[out->nchunk] = groups->n;
+    TileGeom g;
+    g.TE = TE;
+    g.n_etiles = (NE + TE - 1) / TE;
+    g.lds_win = (int)win_max;
+    g.lds_scr = kN3D * TE * NN;
+    g.lds_bytes = std::max((size_t)g.lds_win * 8, (size_t)g.lds_scr * 16) +
+                  (size_t)kN3D * NN * sizeof(double);
+    return g;
+}
+
+size_t mfma_afrag_bytes(int, int NA, int NB, int Nqz, const GroupTable &g)
+{
+    return (size_t)NA * NB * Nqz * g.n * 64 * 32;
+}
+
+hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s)
+{
+    const int64_t n = (int64_t)p.NA * p.NB * p.Nqz * p.groups.n * 64;
+    const int64_t nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL)
+        return hipErrorInvalidConfiguration;
+    if (prec == SSE_BF16X3)
+        hipLaunchKernelGGL(k_prep_afrag<SSE_BF16X3>, dim3((unsigned)nb), dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL(k_prep_afrag<SSE_FP32>, dim3((unsigned)nb), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,
+                                  hipStream_t s)
+{
+    static bool attr_set[2] = {false, false};
+    const void *fn = prec == SSE_BF16X3 ? (const void *)k_sse_mfma_persistent<SSE_BF16X3>
+                                        : (const void *)k_sse_mfma_persistent<SSE_FP32>;
+    const int which = prec == SSE_BF16X3;
+    if (!attr_set[which]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kWinBudget + 16 * 1024));
+        if (e != hipSuccess)
+            return e;
+        attr_set[which] = true;
+    }
+    if (prec == SSE_BF16X3)
+        hipLaunchKernelGGL(k_sse_mfma_persistent<SSE_BF16X3>, dim3(grid), dim3(kBlock), lds_bytes,
+                           s, bl);
+    else
+        hipLaunchKernelGGL(k_sse_mfma_persistent<SSE_FP32>, dim3(grid), dim3(kBlock), lds_bytes, s,
+                           bl);
+    return hipGetLastError();
+}
+
+hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStream_t s)
+{
+    if (p.n_wg <= 0)
+        return hipSuccess;
+    if (p.n_wg > 0x7fffffffLL)
+        return hipErrorInvalidConfiguration;
+    static bool attr_set[2] = {false, false};
+    const void *fn = prec == SSE_BF16X3 ? (const void *)k_sse_mfma<SSE_BF16X3>
+                                        : (const void *)k_sse_mfma<SSE_FP32>;
+    const int which = prec == SSE_BF16X3;
+    if (!attr_set[which]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kWinBudget + 16 * 1024));
+        if (e != hipSuccess)
+            return e;
+        attr_set[which] = true;
+    }
+    if (prec == SSE_BF16X3)
+        hipLaunchKernelGGL(k_sse_mfma<SSE_BF16X3>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes,
+                           s, p);
+    else
+        hipLaunchKernelGGL(k_sse_mfma<SSE_FP32>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s,
+                           p);
+    return hipGetLastError();
+}
+
+}  // namespace sse

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <cstdarg>
 #include <cstdio>
 #include <mutex>
@@ -39,8 +41,10 @@ sse_status hip_fail(hipError_t e, const char *what)
 // One problem instance of a plan.
 struct Instance {
     sse_desc d;
-    TapTable taps;  // sorted and chunked for this instance's tile geometry
+    TapTable taps;      // sorted and chunked for this instance's tile geometry
+    GroupTable groups;  // MFMA path: tap groups per chunk
     TileGeom geom;
+    size_t afrag_bytes = 0;  // MFMA path: workspace for the A-operand fragments
 };
 
 constexpr size_t kStatusBytes = 256;  // status word region at the start of the workspace
@@ -50,14 +54,37 @@ constexpr size_t kStatusBytes = 256;  // status word region at the start of the 
 struct sse_plan_s {
     std::vector<Instance> inst;
     size_t ws_bytes = kStatusBytes;
+    bool batch = false;
+    // ---- batch plans: device tables, built at the first submission
+    std::once_flag tables_once;
+    hipError_t tables_err = hipSuccess;
+    void *d_params = nullptr;
+    int32_t *d_chunk_inst = nullptr, *d_chunk_atom = nullptr;
+    int64_t *d_chunk_start = nullptr;
+    int32_t qbeg[kQueues + 1] = {};
+    int64_t qcount[kQueues] = {};
+    std::vector<size_t> afrag_off;  // per instance, offset of its A fragments in the workspace
+    size_t lds_bytes = 0;
+    int grid = 0;
+    ~sse_plan_s()
+    {
+        hipFree(d_params);
+        hipFree(d_chunk_inst);
+        hipFree(d_chunk_atom);
+        hipFree(d_chunk_start);
+    }
 };
 
 namespace {
 
 struct Ticket {
     hipEvent_t ev = nullptr;
-    uint32_t *host_status = nullptr;  // pinned
+    uint32_t *host_status = nullptr;  // pinned 64-byte block: status word, then check sums
+    int ncheck = 0;                   // sse_check_submit: components checked
+    double tol = 0.0;
+    double *rel_out = nullptr;        // caller's host array for the errors
 };
+constexpr size_t kHostBlock = 64;
 
 std::mutex g_mu;
 std::unordered_map<uint64_t, Ticket> g_tickets;
@@ -78,7 +105,7 @@ sse_status check_desc(const sse_desc *d, const int32_t *w_shift)
 {
     if (!d || !w_shift)
         return fail(SSE_ERR_ARG, "sse_plan: desc and w_shift must be non-NULL");
-    if (d->prec < SSE_FP64 || d->prec > SSE_BF16X3)
+    if (d->prec < SSE_FP64 || d->prec > SSE_FP64C64)
         return fail(SSE_ERR_ARG, "sse_plan: unknown precision %d", d->prec);
     if (d->NA < 1 || d->Nkz < 1 || d->NE < 1)
         return fail(SSE_ERR_SHAPE, "sse_plan: NA, Nkz, NE must be >= 1 (got %d, %d, %d)", d->NA,
@@ -95,6 +122,8 @@ sse_status check_desc(const sse_desc *d, const int32_t *w_shift)
         return fail(SSE_ERR_SHAPE, "sse_plan: Nw=%d outside 1..%d", d->Nw, kMaxTaps);
     if (d->ncomp != 1 && d->ncomp != 2)
         return fail(SSE_ERR_SHAPE, "sse_plan: ncomp=%d, must be 1 or 2", d->ncomp);
+    if (d->tile_e < 0 || d->reserved != 0)
+        return fail(SSE_ERR_ARG, "sse_plan: tile_e must be >= 0 and reserved 0");
     for (int w = 0; w < d->Nw; ++w)
         if (w_shift[w] <= -d->NE || w_shift[w] >= d->NE)
             return fail(SSE_ERR_SHAPE, "sse_plan: |w_shift[%d]|=%d not below NE=%d", w, w_shift[w],
@@ -122,18 +151,23 @@ TapTable sorted_taps(const sse_desc &d, const int32_t *w_shift)
     return t;
 }
 
-sse_status build_instance(const sse_desc *d, const int32_t *w_shift, int te_request, Instance *out)
+sse_status build_instance(const sse_desc *d, const int32_t *w_shift, Instance *out)
 {
+    const int te_request = d ? d->tile_e : 0;
     sse_status st = check_desc(d, w_shift);
     if (st != SSE_OK)
         return st;
     out->d = *d;
     TapTable t = sorted_taps(*d, w_shift);
-    if (d->prec == SSE_FP64) {
+    if (d->prec == SSE_FP64 || d->prec == SSE_FP64C64) {
         out->geom = fp64_geometry(d->Norb, d->NE, t, te_request, &out->taps);
     } else {
-        return fail(SSE_ERR_UNSUPPORTED, "sse_plan: precision %d not available in this build",
-                    d->prec);
+        if (d->Norb > 22)
+            return fail(SSE_ERR_UNSUPPORTED,
+                        "sse_plan: the complex64 (MFMA) precisions support Norb <= 22 (got %d)",
+                        d->Norb);
+        out->geom = mfma_geometry(d->Norb, d->NE, t, te_request, &out->taps, &out->groups);
+        out->afrag_bytes = mfma_afrag_bytes(d->prec, d->NA, d->NB, d->Nqz, out->groups);
     }
     const int64_t nwg = (int64_t)out->geom.n_etiles * d->Nkz * d->NA;
     if (nwg > 0x7fffffffLL)
@@ -142,8 +176,12 @@ sse_status build_instance(const sse_desc *d, const int32_t *w_shift, int te_requ
 }
 
 size_t elem_bytes(int prec) { return prec == SSE_FP64 ? 16 : 8; }
+bool fp64_arith(int prec) { return prec == SSE_FP64 || prec == SSE_FP64C64; }
 
-sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dstatus, hipStream_t s)
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dstatus, void *wsfree,
+                            hipStream_t s)
 {
     const sse_desc &d = I.d;
     hipError_t e = launch_validate_neigh(a.neigh, (int64_t)d.NA * d.NB, d.NA, dstatus, s);
@@ -157,13 +195,13 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
         const char *G = (const char *)a.G + c * g_elems * eb;
         const char *D = (const char *)a.Dt + c * d_elems * eb;
         char *S = (char *)a.Sigma + c * g_elems * eb;
-        if (d.prec == SSE_FP64) {
+        if (d.prec == SSE_FP64 || d.prec == SSE_FP64C64) {
             Fp64Params p{};
             p.neigh = a.neigh;
             p.dH = a.dH;
-            p.G = (const double2 *)G;
-            p.D = (const double2 *)D;
-            p.Sigma = (double2 *)S;
+            p.G = G;
+            p.D = D;
+            p.Sigma = S;
             p.NA = d.NA;
             p.NB = d.NB;
             p.Norb = d.Norb;
@@ -179,12 +217,237 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
             p.alpha_re = d.alpha_re;
             p.alpha_im = d.alpha_im;
             p.taps = I.taps;
-            e = fp64_launch(p, I.geom.lds_bytes, s);
+            e = fp64_launch(p, d.prec == SSE_FP64C64, I.geom.lds_bytes, s);
             if (e != hipSuccess)
                 return hip_fail(e, "fp64 kernel launch");
         } else {
-            return fail(SSE_ERR_UNSUPPORTED, "precision %d not available", d.prec);
+            MfmaPrepParams pp{};
+            pp.D = (const float2 *)D;
+            pp.afrag = wsfree;
+            pp.NA = d.NA;
+            pp.NB = d.NB;
+            pp.Nqz = d.Nqz;
+            pp.Nw = d.Nw;
+            pp.taps = I.taps;
+            pp.groups = I.groups;
+            e = mfma_prep_launch(d.prec, pp, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "MFMA prep launch");
+            MfmaParams p{};
+            p.neigh = a.neigh;
+            p.dH = a.dH;
+            p.G = (const float2 *)G;
+            p.afrag = wsfree;
+            p.Sigma = (float2 *)S;
+            p.NA = d.NA;
+            p.NB = d.NB;
+            p.Norb = d.Norb;
+            p.NN = (int)NN;
+            p.Nkz = d.Nkz;
+            p.Nqz = d.Nqz;
+            p.NE = d.NE;
+            p.Nw = d.Nw;
+            p.TE = I.geom.TE;
+            p.n_etiles = I.geom.n_etiles;
+            p.n_wg = (int64_t)I.geom.n_etiles * d.Nkz * d.NA;
+            p.lds_win = I.geom.lds_win;
+            p.lds_scr = I.geom.lds_scr;
+            p.alpha_re = d.alpha_re;
+            p.alpha_im = d.alpha_im;
+            p.taps = I.taps;
+            p.groups = I.groups;
+            e = mfma_launch(d.prec, p, I.geom.lds_bytes, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "MFMA kernel launch");
         }
+    }
+    return SSE_OK;
+}
+
+// Per-instance static launch parameters (sizes, taps, geometry; no pointers).
+Fp64Params fp64_params(const Instance &I)
+{
+    const sse_desc &d = I.d;
+    Fp64Params p{};
+    p.NA = d.NA;
+    p.NB = d.NB;
+    p.Norb = d.Norb;
+    p.NN = d.Norb * d.Norb;
+    p.Nkz = d.Nkz;
+    p.Nqz = d.Nqz;
+    p.NE = d.NE;
+    p.Nw = d.Nw;
+    p.TE = I.geom.TE;
+    p.n_etiles = I.geom.n_etiles;
+    p.n_wg = (int64_t)I.geom.n_etiles * d.Nkz * d.NA;
+    p.lds_win = I.geom.lds_win;
+    p.alpha_re = d.alpha_re;
+    p.alpha_im = d.alpha_im;
+    p.taps = I.taps;
+    return p;
+}
+
+MfmaParams mfma_params(const Instance &I)
+{
+    const sse_desc &d = I.d;
+    MfmaParams p{};
+    p.NA = d.NA;
+    p.NB = d.NB;
+    p.Norb = d.Norb;
+    p.NN = d.Norb * d.Norb;
+    p.Nkz = d.Nkz;
+    p.Nqz = d.Nqz;
+    p.NE = d.NE;
+    p.Nw = d.Nw;
+    p.TE = I.geom.TE;
+    p.n_etiles = I.geom.n_etiles;
+    p.n_wg = (int64_t)I.geom.n_etiles * d.Nkz * d.NA;
+    p.lds_win = I.geom.lds_win;
+    p.lds_scr = I.geom.lds_scr;
+    p.alpha_re = d.alpha_re;
+    p.alpha_im = d.alpha_im;
+    p.taps = I.taps;
+    p.groups = I.groups;
+    return p;
+}
+
+// Work queues of a batch plan: atoms of all instances, instances in order of
+// decreasing tile cost, dealt round-robin to the eight queues.
+hipError_t build_batch_tables(sse_plan_s *P)
+{
+    const int n = (int)P->inst.size();
+    std::vector<int> order(n);
+    for (int t = 0; t < n; ++t)
+        order[t] = t;
+    auto cost = [&](int t) {
+        const sse_desc &d = P->inst[t].d;
+        return (double)d.NB * d.Nqz * d.Nw * P->inst[t].geom.TE;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<std::vector<int32_t>> qi(kQueues), qa(kQueues);
+    std::vector<std::vector<int64_t>> qs(kQueues);
+    std::vector<int64_t> qtot(kQueues, 0);
+    int64_t c = 0;
+    for (int t : order) {
+        const Instance &I = P->inst[t];
+        const int64_t tiles = (int64_t)I.d.Nkz * I.geom.n_etiles;
+        for (int a = 0; a < I.d.NA; ++a, ++c) {
+            const int x = (int)(c % kQueues);
+            qi[x].push_back(t);
+            qa[x].push_back(a);
+            qs[x].push_back(qtot[x]);
+            qtot[x] += tiles;
+        }
+    }
+    std::vector<int32_t> ci, ca;
+    std::vector<int64_t> cs;
+    for (int x = 0; x < kQueues; ++x) {
+        P->qbeg[x] = (int32_t)ci.size();
+        P->qcount[x] = qtot[x];
+        ci.insert(ci.end(), qi[x].begin(), qi[x].end());
+        ca.insert(ca.end(), qa[x].begin(), qa[x].end());
+        cs.insert(cs.end(), qs[x].begin(), qs[x].end());
+    }
+    P->qbeg[kQueues] = (int32_t)ci.size();
+    const bool fp64 = fp64_arith(P->inst[0].d.prec);
+    const size_t psz = fp64 ? sizeof(Fp64Params) : sizeof(MfmaParams);
+    std::vector<unsigned char> params(psz * n);
+    for (int t = 0; t < n; ++t) {
+        if (fp64) {
+            Fp64Params fp = fp64_params(P->inst[t]);
+            memcpy(params.data() + psz * t, &fp, psz);
+        } else {
+            MfmaParams mp = mfma_params(P->inst[t]);
+            memcpy(params.data() + psz * t, &mp, psz);
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&P->d_params, params.size())) != hipSuccess ||
+        (e = hipMalloc((void **)&P->d_chunk_inst, ci.size() * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&P->d_chunk_atom, ca.size() * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&P->d_chunk_start, cs.size() * 8)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(P->d_params, params.data(), params.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(P->d_chunk_inst, ci.data(), ci.size() * 4, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(P->d_chunk_atom, ca.data(), ca.size() * 4, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(P->d_chunk_start, cs.data(), cs.size() * 8, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    P->grid = std::max(8, 2 * cus);
+    return hipSuccess;
+}
+
+sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t *dstatus,
+                         hipStream_t s)
+{
+    std::call_once(P->tables_once, [&] { P->tables_err = build_batch_tables(P); });
+    if (P->tables_err != hipSuccess)
+        return hip_fail(P->tables_err, "building the batch tables");
+    const int n = (int)P->inst.size();
+    const sse_desc &d0 = P->inst[0].d;
+    hipError_t e;
+    for (int t = 0; t < n; ++t) {
+        e = launch_validate_neigh(args[t].neigh, (int64_t)P->inst[t].d.NA * P->inst[t].d.NB,
+                                  P->inst[t].d.NA, dstatus, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "validate_neigh launch");
+    }
+    unsigned long long *counters = (unsigned long long *)(ws + kStatusBytes);
+    const size_t eb = elem_bytes(d0.prec);
+    for (int c = 0; c < d0.ncomp; ++c) {
+        BatchLaunch bl{};
+        bl.params = P->d_params;
+        bl.chunk_inst = P->d_chunk_inst;
+        bl.chunk_atom = P->d_chunk_atom;
+        bl.chunk_start = P->d_chunk_start;
+        bl.counters = counters;
+        for (int x = 0; x <= kQueues; ++x)
+            bl.qbeg[x] = P->qbeg[x];
+        for (int x = 0; x < kQueues; ++x)
+            bl.qcount[x] = P->qcount[x];
+        for (int t = 0; t < n; ++t) {
+            const sse_desc &d = P->inst[t].d;
+            const size_t NN = (size_t)d.Norb * d.Norb;
+            const size_t g_elems = (size_t)d.Nkz * d.NE * d.NA * NN;
+            const size_t d_elems = (size_t)d.Nqz * d.Nw * d.NA * d.NB * kNF;
+            bl.nkz[t] = d.Nkz;
+            bl.ptr[t].neigh = args[t].neigh;
+            bl.ptr[t].dH = args[t].dH;
+            bl.ptr[t].G = (const char *)args[t].G + c * g_elems * eb;
+            bl.ptr[t].D = (const char *)args[t].Dt + c * d_elems * eb;
+            bl.ptr[t].Sigma = (char *)args[t].Sigma + c * g_elems * eb;
+            bl.ptr[t].aux = ws + P->afrag_off[t];
+            if (!fp64_arith(d.prec)) {
+                MfmaPrepParams pp{};
+                pp.D = (const float2 *)bl.ptr[t].D;
+                pp.afrag = ws + P->afrag_off[t];
+                pp.NA = d.NA;
+                pp.NB = d.NB;
+                pp.Nqz = d.Nqz;
+                pp.Nw = d.Nw;
+                pp.taps = P->inst[t].taps;
+                pp.groups = P->inst[t].groups;
+                e = mfma_prep_launch(d.prec, pp, s);
+                if (e != hipSuccess)
+                    return hip_fail(e, "MFMA prep launch");
+            }
+        }
+        e = launch_clear_u64(counters, kQueues, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "counter clear launch");
+        if (fp64_arith(d0.prec))
+            e = fp64_persistent_launch(bl, d0.prec == SSE_FP64C64, P->grid, P->lds_bytes, s);
+        else
+            e = mfma_persistent_launch(d0.prec, bl, P->grid, P->lds_bytes, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "persistent kernel launch");
     }
     return SSE_OK;
 }
@@ -205,11 +468,12 @@ sse_status sse_plan(const sse_desc *desc, const int32_t *w_shift, sse_plan_t *pl
     if (!p)
         return fail(SSE_ERR_NOMEM, "sse_plan: out of host memory");
     p->inst.resize(1);
-    sse_status st = build_instance(desc, w_shift, 0, &p->inst[0]);
+    sse_status st = build_instance(desc, w_shift, &p->inst[0]);
     if (st != SSE_OK) {
         delete p;
         return st;
     }
+    p->ws_bytes = kStatusBytes + align256(p->inst[0].afrag_bytes);
     *plan = p;
     if (workspace_bytes)
         *workspace_bytes = p->ws_bytes;
@@ -221,25 +485,34 @@ sse_status sse_plan_batch(const sse_desc *descs, const int32_t *const *w_shift, 
 {
     if (!plan || !descs || !w_shift || n < 1)
         return fail(SSE_ERR_ARG, "sse_plan_batch: NULL argument or n < 1");
+    if (n > kMaxBatch)
+        return fail(SSE_ERR_ARG, "sse_plan_batch: n=%d above %d instances", n, kMaxBatch);
     *plan = nullptr;
     sse_plan_s *p = new (std::nothrow) sse_plan_s;
     if (!p)
         return fail(SSE_ERR_NOMEM, "sse_plan_batch: out of host memory");
+    p->batch = true;
     p->inst.resize(n);
+    p->afrag_off.resize(n);
+    size_t ws = 2 * kStatusBytes;  // status word, then the queue counters
     for (int t = 0; t < n; ++t) {
         const sse_desc &d0 = descs[0], &dt = descs[t];
         if (dt.Norb != d0.Norb || dt.ncomp != d0.ncomp || dt.prec != d0.prec ||
-            dt.alpha_re != d0.alpha_re || dt.alpha_im != d0.alpha_im) {
+            dt.alpha_re != d0.alpha_re || dt.alpha_im != d0.alpha_im || dt.N3D != d0.N3D) {
             delete p;
             return fail(SSE_ERR_ARG, "sse_plan_batch: instance %d differs in Norb/ncomp/prec/alpha",
                         t);
         }
-        sse_status st = build_instance(&descs[t], w_shift[t], 0, &p->inst[t]);
+        sse_status st = build_instance(&descs[t], w_shift[t], &p->inst[t]);
         if (st != SSE_OK) {
             delete p;
             return st;
         }
+        p->afrag_off[t] = ws;
+        ws += align256(p->inst[t].afrag_bytes);
+        p->lds_bytes = std::max(p->lds_bytes, p->inst[t].geom.lds_bytes);
     }
+    p->ws_bytes = ws;
     *plan = p;
     if (workspace_bytes)
         *workspace_bytes = p->ws_bytes;
@@ -247,6 +520,132 @@ sse_status sse_plan_batch(const sse_desc *descs, const int32_t *const *w_shift, 
 }
 
 void sse_plan_destroy(sse_plan_t plan) { delete plan; }
+
+static sse_status ticket_acquire(Ticket *tk)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_tickets.size() >= kMaxInFlight)
+            return fail(SSE_ERR_BUSY, "sse_submit: %zu submissions in flight", g_tickets.size());
+        if (!g_pinned_free.empty()) {
+            tk->host_status = g_pinned_free.back();
+            g_pinned_free.pop_back();
+        }
+        if (!g_event_free.empty()) {
+            tk->ev = g_event_free.back();
+            g_event_free.pop_back();
+        }
+    }
+    hipError_t e;
+    if (!tk->host_status) {
+        e = hipHostMalloc((void **)&tk->host_status, kHostBlock, hipHostMallocDefault);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipHostMalloc");
+    }
+    if (!tk->ev) {
+        e = hipEventCreateWithFlags(&tk->ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+    }
+    *tk->host_status = 0xffffffffu;
+    return SSE_OK;
+}
+
+static void ticket_release(const Ticket &tk)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (tk.host_status)
+        g_pinned_free.push_back(tk.host_status);
+    if (tk.ev)
+        g_event_free.push_back(tk.ev);
+}
+
+// Copies the device status (and check sums) to the ticket's pinned block,
+// records its event and registers it.
+static sse_status ticket_finish_enqueue(Ticket &tk, const void *dstatus, size_t bytes,
+                                        hipStream_t s, uint64_t *ticket)
+{
+    hipError_t e = hipMemcpyAsync(tk.host_status, dstatus, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(tk.ev, s);
+    if (e != hipSuccess) {
+        ticket_release(tk);
+        return hip_fail(e, "status copy / event record");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    *ticket = g_next_ticket++;
+    g_tickets[*ticket] = tk;
+    return SSE_OK;
+}
+
+sse_status sse_check_submit(sse_plan_t plan, const sse_args *args, const int32_t *blocks,
+                            int32_t nblocks, double tol, double *rel_err, void *workspace,
+                            size_t workspace_bytes, void *stream, uint64_t *ticket)
+{
+    if (!plan || !args || !blocks || !rel_err || !ticket || nblocks < 1)
+        return fail(SSE_ERR_ARG, "sse_check_submit: NULL argument or nblocks < 1");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_check_submit: needs a single-instance plan");
+    const Instance &I = plan->inst[0];
+    const sse_desc &d = I.d;
+    if (d.prec == SSE_FP64)
+        return fail(SSE_ERR_ARG, "sse_check_submit: checks complex64 results only");
+    if (d.Norb > 22)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_check_submit: Norb <= 22");
+    const size_t need = kStatusBytes + (size_t)16 * nblocks * d.ncomp;
+    if (!workspace || workspace_bytes < need)
+        return fail(SSE_ERR_ARG, "sse_check_submit: workspace of %zu bytes needed", need);
+    const sse_args &a = args[0];
+    if (!a.neigh || !a.dH || !a.G || !a.Dt || !a.Sigma)
+        return fail(SSE_ERR_ARG, "sse_check_submit: NULL tensor pointer");
+    hipStream_t s = (hipStream_t)stream;
+    Ticket tk;
+    sse_status st = ticket_acquire(&tk);
+    if (st != SSE_OK)
+        return st;
+    tk.ncheck = d.ncomp;
+    tk.tol = tol;
+    tk.rel_out = rel_err;
+    char *ws = (char *)workspace;
+    uint32_t *dstatus = (uint32_t *)ws;
+    double *sums = (double *)(ws + 16);
+    hipError_t e = launch_clear_status(dstatus, s);
+    if (e == hipSuccess)
+        e = launch_validate_neigh(a.neigh, (int64_t)d.NA * d.NB, d.NA, dstatus, s);
+    const size_t NN = (size_t)d.Norb * d.Norb;
+    const size_t g_elems = (size_t)d.Nkz * d.NE * d.NA * NN;
+    const size_t d_elems = (size_t)d.Nqz * d.Nw * d.NA * d.NB * kNF;
+    for (int c = 0; c < d.ncomp && e == hipSuccess; ++c) {
+        CheckParams cp{};
+        cp.neigh = a.neigh;
+        cp.dH = a.dH;
+        cp.G = (const float2 *)a.G + c * g_elems;
+        cp.D = (const float2 *)a.Dt + c * d_elems;
+        cp.Sigma = (const float2 *)a.Sigma + c * g_elems;
+        cp.blocks = blocks;
+        cp.nblocks = nblocks;
+        cp.partial = (double *)(ws + kStatusBytes) + (size_t)2 * nblocks * c;
+        cp.status = dstatus;
+        cp.NA = d.NA;
+        cp.NB = d.NB;
+        cp.Norb = d.Norb;
+        cp.NN = (int)NN;
+        cp.Nkz = d.Nkz;
+        cp.Nqz = d.Nqz;
+        cp.NE = d.NE;
+        cp.Nw = d.Nw;
+        cp.alpha_re = d.alpha_re;
+        cp.alpha_im = d.alpha_im;
+        for (int t = 0; t < I.taps.n; ++t)
+            cp.shift[I.taps.w[t]] = I.taps.s[t];
+        e = check_launch(cp, sums + 2 * c, s);
+    }
+    if (e != hipSuccess) {
+        ticket_release(tk);
+        return hip_fail(e, "check launch");
+    }
+    return ticket_finish_enqueue(tk, ws, 16 + 16 * d.ncomp, s, ticket);
+}
 
 sse_status sse_submit(sse_plan_t plan, const sse_args *args, void *workspace,
                       size_t workspace_bytes, void *stream, uint64_t *ticket)
@@ -262,60 +661,24 @@ sse_status sse_submit(sse_plan_t plan, const sse_args *args, void *workspace,
     }
     hipStream_t s = (hipStream_t)stream;
     Ticket tk;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (g_tickets.size() >= kMaxInFlight)
-            return fail(SSE_ERR_BUSY, "sse_submit: %zu submissions in flight", g_tickets.size());
-        if (!g_pinned_free.empty()) {
-            tk.host_status = g_pinned_free.back();
-            g_pinned_free.pop_back();
-        }
-        if (!g_event_free.empty()) {
-            tk.ev = g_event_free.back();
-            g_event_free.pop_back();
-        }
-    }
-    hipError_t e;
-    if (!tk.host_status) {
-        e = hipHostMalloc((void **)&tk.host_status, sizeof(uint32_t), hipHostMallocDefault);
-        if (e != hipSuccess)
-            return hip_fail(e, "hipHostMalloc");
-    }
-    if (!tk.ev) {
-        e = hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming);
-        if (e != hipSuccess)
-            return hip_fail(e, "hipEventCreate");
-    }
-    auto give_back = [&]() {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_pinned_free.push_back(tk.host_status);
-        g_event_free.push_back(tk.ev);
-    };
-    *tk.host_status = 0xffffffffu;
+    sse_status st = ticket_acquire(&tk);
+    if (st != SSE_OK)
+        return st;
     uint32_t *dstatus = (uint32_t *)workspace;
-    e = launch_clear_status(dstatus, s);
+    hipError_t e = launch_clear_status(dstatus, s);
     if (e != hipSuccess) {
-        give_back();
+        ticket_release(tk);
         return hip_fail(e, "clear_status launch");
     }
-    for (size_t t = 0; t < plan->inst.size(); ++t) {
-        sse_status st = enqueue_instance(plan->inst[t], args[t], dstatus, s);
-        if (st != SSE_OK) {
-            give_back();
-            return st;
-        }
+    if (plan->batch)
+        st = enqueue_batch(plan, args, (char *)workspace, dstatus, s);
+    else
+        st = enqueue_instance(plan->inst[0], args[0], dstatus, (char *)workspace + kStatusBytes, s);
+    if (st != SSE_OK) {
+        ticket_release(tk);
+        return st;
     }
-    e = hipMemcpyAsync(tk.host_status, dstatus, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipEventRecord(tk.ev, s);
-    if (e != hipSuccess) {
-        give_back();
-        return hip_fail(e, "status copy / event record");
-    }
-    std::lock_guard<std::mutex> lk(g_mu);
-    *ticket = g_next_ticket++;
-    g_tickets[*ticket] = tk;
-    return SSE_OK;
+    return ticket_finish_enqueue(tk, dstatus, sizeof(uint32_t), s, ticket);
 }
 
 static sse_status finish_ticket(uint64_t ticket, bool block)
@@ -339,17 +702,29 @@ static sse_status finish_ticket(uint64_t ticket, bool block)
         g_tickets.erase(it);
     }
     const uint32_t hs = *tk.host_status;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_pinned_free.push_back(tk.host_status);
-        g_event_free.push_back(tk.ev);
-    }
+    double sums[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 2 * tk.ncheck; ++c)
+        sums[c] = ((const double *)((const char *)tk.host_status + 16))[c];
+    ticket_release(tk);
     if (e != hipSuccess)
         return hip_fail(e, "waiting for a submission");
     if (hs & kStatusBadNeigh)
         return fail(SSE_ERR_NEIGH, "a neighbour index is outside [0, NA)");
+    if (hs & kStatusBadBlock)
+        return fail(SSE_ERR_ARG, "sse_check_submit: a listed block is outside the output");
     if (hs != 0)
         return fail(SSE_ERR_DEVICE, "device status word 0x%x", hs);
+    if (tk.ncheck > 0) {
+        bool miss = false;
+        for (int c = 0; c < tk.ncheck; ++c) {
+            const double d2 = sums[2 * c], r2 = sums[2 * c + 1];
+            const double rel = r2 > 0.0 ? sqrt(d2 / r2) : sqrt(d2);
+            tk.rel_out[c] = rel;
+            miss |= !(rel <= tk.tol);
+        }
+        if (miss)
+            return fail(SSE_ERR_TOLERANCE, "sampled error above tolerance %g", tk.tol);
+    }
     return SSE_OK;
 }
 

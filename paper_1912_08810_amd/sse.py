@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libsse.so")
 
 OK, PENDING, ERR_ARG, ERR_SHAPE, ERR_NEIGH, ERR_NOMEM, ERR_BUSY, ERR_TOLERANCE, ERR_DEVICE, \
     ERR_UNSUPPORTED = range(10)
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, FP64C64 = 0, 1, 2, 3
 STATUS_NAMES = ["SSE_OK", "SSE_PENDING", "SSE_ERR_ARG", "SSE_ERR_SHAPE", "SSE_ERR_NEIGH",
                 "SSE_ERR_NOMEM", "SSE_ERR_BUSY", "SSE_ERR_TOLERANCE", "SSE_ERR_DEVICE",
                 "SSE_ERR_UNSUPPORTED"]
@@ -25,7 +25,8 @@ class sse_desc(ctypes.Structure):
     _fields_ = [("NA", ctypes.c_int32), ("NB", ctypes.c_int32), ("Norb", ctypes.c_int32),
                 ("N3D", ctypes.c_int32), ("Nkz", ctypes.c_int32), ("Nqz", ctypes.c_int32),
                 ("NE", ctypes.c_int32), ("Nw", ctypes.c_int32), ("ncomp", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("alpha_re", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("tile_e", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("alpha_re", ctypes.c_double),
                 ("alpha_im", ctypes.c_double)]
 
 
@@ -52,12 +53,15 @@ def _load():
     L.sse_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
     L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
                              c.POINTER(c.c_uint64)]
+    L.sse_check_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_int32, c.c_double, vp, vp,
+                                   c.c_size_t, vp, c.POINTER(c.c_uint64)]
     L.sse_poll.argtypes = [c.c_uint64]
     L.sse_wait.argtypes = [c.c_uint64]
     L.sse_plan_destroy.argtypes = [vp]
     L.sse_plan_destroy.restype = None
     L.sse_last_error.restype = c.c_char_p
-    for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_submit, L.sse_poll, L.sse_wait):
+    for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_submit, L.sse_poll, L.sse_wait,
+              L.sse_check_submit):
         f.restype = c.c_int
     return L
 
@@ -65,8 +69,8 @@ def _load():
 lib = _load()
 
 # Every symbol include/sse.h declares (checked by the CPU test of the library).
-EXPORTS = ["sse_plan", "sse_plan_batch", "sse_compute", "sse_submit", "sse_poll", "sse_wait",
-           "sse_plan_destroy", "sse_last_error"]
+EXPORTS = ["sse_check_submit", "sse_compute", "sse_last_error", "sse_plan", "sse_plan_batch",
+           "sse_plan_destroy", "sse_poll", "sse_submit", "sse_wait"]
 
 
 def last_error() -> str:
@@ -95,9 +99,10 @@ def _stream(s):
     return s.cuda_stream
 
 
-def make_desc(NA, NB, Norb, Nkz, Nqz, NE, Nw, ncomp=1, prec=FP64, alpha=1j, N3D=3):
+def make_desc(NA, NB, Norb, Nkz, Nqz, NE, Nw, ncomp=1, prec=FP64, alpha=1j, N3D=3, tile_e=0):
     alpha = complex(alpha)
-    return sse_desc(NA, NB, Norb, N3D, Nkz, Nqz, NE, Nw, ncomp, prec, alpha.real, alpha.imag)
+    return sse_desc(NA, NB, Norb, N3D, Nkz, Nqz, NE, Nw, ncomp, prec, tile_e, 0, alpha.real,
+                    alpha.imag)
 
 
 class Plan:
@@ -173,3 +178,30 @@ def sse_poll(ticket: int) -> int:
 def sse_wait(ticket: int, check=True) -> int:
     st = lib.sse_wait(ticket)
     return _check(st, "sse_wait") if check else st
+
+
+def check_workspace_bytes(nblocks: int, ncomp: int) -> int:
+    return 256 + 16 * nblocks * ncomp
+
+
+class CheckTicket:
+    """A pending sse_check_submit: ``rel_err`` is filled when it finishes."""
+
+    def __init__(self, ticket: int, rel_err):
+        self.ticket = ticket
+        self.rel_err = rel_err
+
+
+def sse_check_submit(plan: Plan, item, blocks, tol, workspace, stream=None) -> CheckTicket:
+    """item: (neigh, dH, G, Dt, Sigma); blocks: device int32 tensor [n, 3]."""
+    ncomp = plan.descs[0].ncomp
+    rel = (ctypes.c_double * ncomp)()
+    t = ctypes.c_uint64()
+    arr = _args([item])
+    n = int(blocks.shape[0]) if hasattr(blocks, "shape") else len(blocks) // 3
+    _check(lib.sse_check_submit(plan.handle, arr, _ptr(blocks), n, float(tol),
+                                ctypes.cast(rel, ctypes.c_void_p), _ptr(workspace),
+                                workspace.numel() * workspace.element_size()
+                                if hasattr(workspace, "numel") else check_workspace_bytes(n, ncomp),
+                                _stream(stream), ctypes.byref(t)), "sse_check_submit")
+    return CheckTicket(t.value, rel)

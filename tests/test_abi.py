@@ -85,3 +85,28 @@ def test_submit_rejects_small_workspace_before_any_device_call():
     t = ctypes.c_uint64()
     st = sse.lib.sse_submit(p.handle, args, ctypes.c_void_p(8), 0, None, ctypes.byref(t))
     assert st == sse.ERR_ARG and "workspace" in sse.last_error()
+
+
+def test_batch_plan_validation():
+    sse = _sse()
+    d1 = sse.make_desc(16, 4, 4, 3, 3, 64, 4)
+    d2 = sse.make_desc(30, 4, 5, 3, 3, 40, 6)  # different Norb
+    with pytest.raises(sse.SSEError) as ei:
+        sse.sse_plan_batch([d1, d2], [np.arange(1, 5), np.arange(1, 7)])
+    assert ei.value.status == sse.ERR_ARG
+    p = sse.sse_plan_batch([d1, sse.make_desc(30, 4, 4, 3, 3, 40, 6)],
+                           [np.arange(1, 5), np.arange(1, 7)])
+    assert p.workspace_bytes >= 512
+    many = [d1] * 65
+    with pytest.raises(sse.SSEError):
+        sse.sse_plan_batch(many, [np.arange(1, 5)] * 65)
+
+
+def test_tile_e_and_reserved_fields():
+    sse = _sse()
+    assert plan_status(tile_e=3)[0] == 0
+    assert plan_status(tile_e=-1)[0] == sse.ERR_ARG
+    d = sse.make_desc(16, 4, 4, 3, 3, 64, 4)
+    d.reserved = 1
+    with pytest.raises(sse.SSEError):
+        sse.sse_plan(d, np.arange(1, 5))

@@ -22,19 +22,7 @@ def _sse():
 
 
 def run(dp: gu.DeviceProblem, alpha=1j, prec=0):
-    import torch
-    sse = _sse()
-    p = dp.prob
-    desc = sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw, ncomp=dp.ncomp, prec=prec,
-                         alpha=alpha)
-    plan = sse.sse_plan(desc, p.shifts())
-    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
-    print(f"[case] NA={p.NA} NB={p.NB} Norb={p.Norb} Nkz={p.Nkz} Nqz={p.Nqz} NE={p.NE} "
-          f"Nw={p.Nw} ncomp={dp.ncomp} prec={prec}", flush=True)
-    st = sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws,
-                         torch.cuda.current_stream(), check=False)
-    torch.cuda.synchronize()
-    return st
+    return gu.run_sse(dp, alpha=alpha, prec=prec)
 
 
 def check_full(dp, alpha=1j):

@@ -36,6 +36,13 @@ def parse():
                     help="precision forms timed after the binary64 headline ('' = none)")
     ap.add_argument("--only", default="",
                     help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
+    ap.add_argument("--batch", default="fp64,bf16x3",
+                    help="precisions of the 48-instance batched run ('' = skip)")
+    ap.add_argument("--batch-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serving-jobs", type=int, default=8,
+                    help="jobs of the serving run (0 = skip)")
+    ap.add_argument("--serving-half-load", action="store_true",
+                    help="also serve at half the measured capacity (service latency)")
     ap.add_argument("--profile-steps", action="store_true",
                     help="print a progress line per step (for profiler runs)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -94,6 +101,138 @@ def cpu_baseline(prob, seed, target_s):
         "plain_gflops": round(per_block_plain * n / t / 1e9, 3),
         "extrapolated_full_job_s": round(t / n * prob.Nkz * prob.NE * prob.NA * 2, 1),
     }
+
+
+def batch_section(args, torch, sse, configs, DeviceProblem, log):
+    """48 uneven instances (one component each) in HBM-budgeted waves; each wave
+    is one persistent launch; tile shapes from the autotuner's cache."""
+    from paper_1912_08810_amd import autotune
+    cache = autotune.load_cache()
+    insts = configs.batch_instances(configs.SEED, 48)
+    out = {}
+    for name in [x for x in args.batch.split(",") if x]:
+        prec = {"fp64": sse.FP64, "fp32": sse.FP32, "bf16x3": sse.BF16X3}[name]
+        esz = 16 if prec == sse.FP64 else 8
+        per = lambda p: (2 * p.g_elems() + p.d_elems()) * esz + p.NA * p.NB * p.NN * 3 * 8
+        order = sorted(range(len(insts)), key=lambda i: -insts[i].flops())
+        waves, cur, used = [], [], 0
+        for i in order:
+            need = per(insts[i])
+            if cur and (used + need > args.batch_budget_gb * 1e9 or len(cur) == 64):
+                waves.append(cur)
+                cur, used = [], 0
+            cur.append(i)
+            used += need
+        waves.append(cur)
+        wave_s, flops, tiles = [], 0.0, {}
+        one_by_one = None
+        for wi, wave in enumerate(waves):
+            dps = [DeviceProblem(insts[i], 5000 + i, ncomp=1, fp32=prec != sse.FP64)
+                   for i in wave]
+            descs = []
+            for i in wave:
+                p = insts[i]
+                te = autotune.tile_for(prec, p.Norb, p.NE, p.Nw, cache)
+                tiles[i] = te
+                descs.append(sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw,
+                                           prec=prec, tile_e=te))
+            plan = sse.sse_plan_batch(descs, [insts[i].shifts() for i in wave])
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+            stream = torch.cuda.current_stream()
+            items = [(d.neigh, d.dH, d.G, d.D, d.Sigma) for d in dps]
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t = sse.sse_submit(plan, items, ws, stream)
+            e1.record(stream)
+            sse.sse_wait(t)
+            e1.synchronize()
+            wave_s.append(e0.elapsed_time(e1) / 1e3)
+            flops += sum(insts[i].flops() for i in wave)
+            log(f"batch {name} wave {wi}: {len(wave)} instances, {wave_s[-1]:.3f} s")
+            if wi == 0 and name == "fp64":
+                # the same wave, one instance after the other (one-shot launches)
+                e0.record(stream)
+                for i, d in zip(wave, dps):
+                    p = insts[i]
+                    sp = sse.sse_plan(descs[wave.index(i)], p.shifts())
+                    w1 = torch.empty(max(sp.workspace_bytes, 256), dtype=torch.uint8,
+                                     device="cuda")
+                    sse.sse_compute(sp, d.neigh, d.dH, d.G, d.D, d.Sigma, w1, stream)
+                e1.record(stream)
+                e1.synchronize()
+                one_by_one = e0.elapsed_time(e1) / 1e3
+                log(f"batch {name} wave 0 one-by-one: {one_by_one:.3f} s")
+            del dps, ws, items
+            torch.cuda.empty_cache()
+        total = sum(wave_s)
+        out[name] = {"instances": len(insts), "waves": len(waves),
+                     "wave_s": [round(x, 3) for x in wave_s], "total_s": round(total, 3),
+                     "value": round(flops / total / 1e9, 1), "unit": "GFLOP/s",
+                     "storage": "complex128" if prec == sse.FP64 else "complex64",
+                     "budget_gb": args.batch_budget_gb,
+                     "tile_e_tuned": bool(cache)}
+        if one_by_one is not None:
+            out[name]["wave0_one_by_one_s"] = round(one_by_one, 3)
+            out[name]["wave0_persistent_speedup"] = round(one_by_one / wave_s[0], 3)
+    return out
+
+
+def serving_section(args, torch, sse, configs, log):
+    """Jobs from the batch size distribution, Poisson arrivals at 200 jobs/s,
+    10 SCBA iterations each, complex64 (bf16 hi/lo MFMA) at the fp32 tolerance
+    with binary64 fallback; compared with the plain per-job path (binary64, one
+    job at a time, inputs copied in and results out every iteration)."""
+    from paper_1912_08810_amd import serving
+    from ssegen.device_problem import DeviceProblem
+    probs = configs.batch_instances(configs.SEED + 1, args.serving_jobs)
+    jobs = serving.make_jobs(probs, rate=200.0, seed=configs.SEED)
+    srv = serving.Server(budget_bytes=200e9, slots=4, prec=sse.BF16X3, tol=1e-5)
+    res = srv.run(jobs, log=log)
+    sat = serving.summarize(res)
+    out = {"saturated": dict(sat, arrival_rate=200.0, label="saturated (offered load far above "
+                             "capacity; latency is queueing-dominated)")}
+    # plain per-job path on the first job: host -> device copies of G and D~
+    # (complex128), binary64 compute, Sigma back to the host, every iteration
+    p = probs[0]
+    dp = DeviceProblem(p, 77, ncomp=2)
+    hostG = torch.empty(dp.G.shape, dtype=dp.G.dtype, pin_memory=True)
+    hostD = torch.empty(dp.D.shape, dtype=dp.D.dtype, pin_memory=True)
+    hostS = torch.empty(dp.Sigma.shape, dtype=dp.Sigma.dtype, pin_memory=True)
+    hostG.copy_(dp.G)
+    hostD.copy_(dp.D)
+    desc = sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw, ncomp=2, prec=sse.FP64)
+    plan = sse.sse_plan(desc, p.shifts())
+    ws = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(10):
+        dp.G.copy_(hostG, non_blocking=True)
+        dp.D.copy_(hostD, non_blocking=True)
+        sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws,
+                        torch.cuda.current_stream())
+        hostS.copy_(dp.Sigma, non_blocking=True)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_tflops = 2 * p.flops() * 10 / t_plain / 1e12
+    del dp, hostG, hostD, hostS, ws
+    torch.cuda.empty_cache()
+    # serial resident complex64 (one slot): isolates the gain of overlapping jobs
+    serial = serving.Server(budget_bytes=200e9, slots=1, prec=sse.BF16X3, tol=1e-5)
+    j0 = serving.make_jobs(probs[:2], rate=1e9, seed=configs.SEED)
+    rs = serial.run(j0)
+    ser = serving.summarize(rs)
+    out["plain_per_job"] = {"tflops": round(plain_tflops, 3), "job_s": round(t_plain, 3),
+                            "job": f"NA={p.NA} NE={p.NE} Nw={p.Nw}", "path": "fp64, copies in/out"}
+    out["serial_resident_c64"] = {"tflops": ser["tflops"], "jobs": ser["jobs"]}
+    out["speedup_vs_plain"] = round(sat["tflops"] / plain_tflops, 2)
+    out["speedup_vs_serial_resident"] = round(sat["tflops"] / ser["tflops"], 2)
+    if args.serving_half_load:
+        rate = 0.5 * sat["jobs_per_s"]
+        jobs2 = serving.make_jobs(probs, rate=rate, seed=configs.SEED + 7)
+        r2 = serving.Server(budget_bytes=200e9, slots=4, prec=sse.BF16X3, tol=1e-5).run(jobs2)
+        out["half_capacity"] = dict(serving.summarize(r2), arrival_rate=round(rate, 4))
+    return out
 
 
 def main():
@@ -211,6 +350,13 @@ def main():
     }
     for f in form_out.values():
         f["speedup_vs_fp64"] = round(med / (f["ms_per_step"] / 1e3), 2)
+    log = (lambda m: print(m, flush=True)) if args.profile_steps else (lambda m: None)
+    if args.only:
+        args.batch, args.serving_jobs = "", 0
+    if args.batch:
+        out["batch"] = batch_section(args, torch, sse, configs, DeviceProblem, log)
+    if args.serving_jobs > 0:
+        out["serving"] = serving_section(args, torch, sse, configs, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

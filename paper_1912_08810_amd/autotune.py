@@ -1,0 +1,118 @@
+"""Tile-shape autotuner for batched launches.
+
+For every size bucket (energy count x frequency count) and precision, the tuner
+times the persistent batched kernel on a representative instance for each
+candidate tile shape (energies per tile, ``sse_desc.tile_e``) and keeps the
+fastest.  The search is exhaustive over the candidates -- the idea of choosing
+a decomposition by searching all feasible tile sizes (the paper searches
+data-movement tilings exhaustively, Sec. 4.1) applied to the on-chip tile.
+Results are cached as JSON keyed by (arch, precision, Norb).
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+
+import numpy as np
+
+from . import configs
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+# Buckets over (NE, Nw): upper bounds, inclusive.
+NE_EDGES = (600, 1000, 1500)
+NW_EDGES = (20, 30, 40)
+
+
+def bucket_of(NE: int, Nw: int):
+    bi = next((i for i, x in enumerate(NE_EDGES) if NE <= x), len(NE_EDGES) - 1)
+    bj = next((j for j, x in enumerate(NW_EDGES) if Nw <= x), len(NW_EDGES) - 1)
+    return bi, bj
+
+
+def candidates(prec: int, Norb: int):
+    nn = Norb * Norb
+    tmax = max(1, (1024 if prec in (0, 3) else 512) // nn)
+    c = sorted({tmax, max(1, tmax * 3 // 4), max(1, tmax // 2), max(1, tmax // 4), 1},
+               reverse=True)
+    return c
+
+
+def _key(prec: int, Norb: int) -> str:
+    return f"gfx950/prec={prec}/Norb={Norb}"
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def tile_for(prec: int, Norb: int, NE: int, Nw: int, cache: dict | None = None) -> int:
+    """Tuned tile_e for an instance; 0 (library default) if the bucket is untuned."""
+    cache = load_cache() if cache is None else cache
+    tab = cache.get(_key(prec, Norb))
+    if not tab:
+        return 0
+    bi, bj = bucket_of(NE, Nw)
+    return int(tab.get(f"{bi},{bj}", {}).get("tile_e", 0))
+
+
+def _time_instance(prob, prec, tile_e, reps, seed):
+    import torch
+    from ssegen.device_problem import DeviceProblem
+    from . import sse
+    fp32 = prec in (1, 2, 3)
+    dp = DeviceProblem(prob, seed, ncomp=1, fp32=fp32)
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                         prec=prec, tile_e=tile_e)
+    plan = sse.sse_plan_batch([desc], [prob.shifts()])
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    item = [(dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma)]
+    sse.sse_wait(sse.sse_submit(plan, item, ws, stream))  # warm-up, builds tables
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t = sse.sse_submit(plan, item, ws, stream)
+        e1.record(stream)
+        sse.sse_wait(t)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del dp, ws
+    return statistics.median(ts)
+
+
+def tune(prec: int, Norb: int = 10, NA: int = 192, reps: int = 3, seed: int = 7,
+         path: str = CACHE, log=print) -> dict:
+    """Exhaustive search over the tile candidates for every bucket; updates the cache."""
+    tab = {}
+    ne_lo = (200,) + tuple(x + 1 for x in NE_EDGES[:-1])
+    nw_lo = (10,) + tuple(x + 1 for x in NW_EDGES[:-1])
+    for bi, (lo, hi) in enumerate(zip(ne_lo, NE_EDGES)):
+        for bj, (wl, wh) in enumerate(zip(nw_lo, NW_EDGES)):
+            prob = configs.Problem(NA=NA, NB=4, Norb=Norb, Nkz=5, Nqz=5, NE=(lo + hi) // 2,
+                                   Nw=(wl + wh) // 2)
+            times = {}
+            for te in candidates(prec, Norb):
+                times[te] = _time_instance(prob, prec, te, reps, seed)
+            best = min(times, key=times.get)
+            tab[f"{bi},{bj}"] = {"tile_e": best, "NE": prob.NE, "Nw": prob.Nw,
+                                 "ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}}
+            log(f"tune prec={prec} bucket NE<={hi} Nw<={wh}: best tile_e={best} "
+                f"({', '.join(f'{k}:{v*1e3:.1f}ms' for k, v in times.items())})")
+    cache = load_cache(path)
+    cache[_key(prec, Norb)] = tab
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    return tab
+
+
+if __name__ == "__main__":
+    import sys
+    precs = [int(x) for x in (sys.argv[1:] or ["0", "2"])]
+    for p in precs:
+        tune(p)

@@ -34,12 +34,14 @@ __global__ void k_validate_neigh(const int32_t *__restrict__ neigh, int64_t n, i
 
 hipError_t launch_clear_status(uint32_t *status, hipStream_t s)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, status);
     return hipGetLastError();
 }
 
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
@@ -52,6 +54,7 @@ hipError_t launch_validate_neigh(const int32_t *neigh, int64_t n, int32_t NA, ui
         g = 1024;
     if (g < 1)
         g = 1;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_validate_neigh, dim3((unsigned)g), dim3(256), 0, s, neigh, n, NA, status);
     return hipGetLastError();
 }

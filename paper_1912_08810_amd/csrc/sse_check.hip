@@ -199,10 +199,12 @@ hipError_t check_launch(const CheckParams &p, double *out, hipStream_t s)
             return e;
         attr = true;
     }
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_check, dim3(p.nblocks), dim3(kBlock), lds, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(64), 0, s, p.partial, p.nblocks, out);
     return hipGetLastError();
 }

@@ -30,11 +30,9 @@ namespace sse {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kR = 4;
-constexpr int kPmax = kBlock * kR;
-// LDS per workgroup: two workgroups share one CU's 160 KiB.
-constexpr size_t kLdsBudget = 78 * 1024;
+constexpr int kBlock = fp64k::kBlock;
+constexpr int kR = fp64k::kR;
+constexpr size_t kLdsBudget = fp64k::kLdsBudget;
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of logical tiles so tiles that read the same G rows (the
@@ -316,37 +314,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLa
 
 }  // namespace
 
-TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out)
-{
-    const int NN = Norb * Norb;
-    int TE = kPmax / NN;
-    if (te_request > 0)
-        TE = std::min(TE, te_request);
-    TE = std::max(1, std::min(TE, NE));
-    const size_t a_bytes = (size_t)kN3D * NN * sizeof(double);
-    const long budget = (long)((kLdsBudget - a_bytes) / sizeof(double2));
-
-    *out = taps;
-    out->nchunk = 0;
-    int t = 0;
-    long win_max = 0;
-    while (t < taps.n) {
-        int u = t + 1;
-        while (u < taps.n && kPmax + (long)(taps.s[t] - taps.s[u]) * NN <= budget)
-            ++u;
-        out->cb[out->nchunk++] = t;
-        win_max = std::max(win_max, kPmax + (long)(taps.s[t] - taps.s[u - 1]) * NN);
-        t = u;
-    }
-    out->cb[out->nchunk] = taps.n;
-    TileGeom g;
-    g.TE = TE;
-    g.n_etiles = (NE + TE - 1) / TE;
-    g.lds_win = (int)std::max(win_max, (long)kN3D * TE * NN);
-    g.lds_bytes = (size_t)g.lds_win * sizeof(double2) + a_bytes;
-    return g;
-}
-
 template <typename K>
 static hipError_t set_lds_attr(K kernel, bool &done)
 {
@@ -367,10 +334,13 @@ hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, siz
                        : set_lds_attr(k_sse_fp64_persistent<double2>, done[0]);
     if (e != hipSuccess)
         return e;
-    if (c64)
+    if (c64) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_fp64_persistent<float2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_fp64_persistent<double2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
+    }
     return hipGetLastError();
 }
 
@@ -385,10 +355,13 @@ hipError_t fp64_launch(const Fp64Params &p, bool c64, size_t lds_bytes, hipStrea
                        : set_lds_attr(k_sse_fp64<double2>, done[0]);
     if (e != hipSuccess)
         return e;
-    if (c64)
+    if (c64) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_fp64<float2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_fp64<double2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
+    }
     return hipGetLastError();
 }
 

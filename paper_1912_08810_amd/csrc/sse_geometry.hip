@@ -1,0 +1,84 @@
+// sse_geometry.hip -- host-side tile geometry of the kernels: energies per
+// tile, tap chunks whose G window fits the LDS budget, MFMA tap groups, LDS
+// bytes and workspace sizes.  Host code only (also built by the host-side
+// runtime test with a stand-in HIP header).
+#include <algorithm>
+
+#include "sse_internal.h"
+
+namespace sse {
+
+TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out)
+{
+    const int NN = Norb * Norb;
+    int TE = fp64k::kPmax / NN;
+    if (te_request > 0)
+        TE = std::min(TE, te_request);
+    TE = std::max(1, std::min(TE, NE));
+    const size_t a_bytes = (size_t)kN3D * NN * sizeof(double);
+    const long budget = (long)((fp64k::kLdsBudget - a_bytes) / sizeof(double2));
+
+    *out = taps;
+    out->nchunk = 0;
+    int t = 0;
+    long win_max = 0;
+    while (t < taps.n) {
+        int u = t + 1;
+        while (u < taps.n && fp64k::kPmax + (long)(taps.s[t] - taps.s[u]) * NN <= budget)
+            ++u;
+        out->cb[out->nchunk++] = t;
+        win_max = std::max(win_max, fp64k::kPmax + (long)(taps.s[t] - taps.s[u - 1]) * NN);
+        t = u;
+    }
+    out->cb[out->nchunk] = taps.n;
+    TileGeom g;
+    g.TE = TE;
+    g.n_etiles = (NE + TE - 1) / TE;
+    g.lds_win = (int)std::max(win_max, (long)kN3D * TE * NN);
+    g.lds_bytes = (size_t)g.lds_win * sizeof(double2) + a_bytes;
+    return g;
+}
+
+TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out,
+                       GroupTable *groups)
+{
+    const int NN = Norb * Norb;
+    int TE = mfmak::kPwg / NN;
+    if (te_request > 0)
+        TE = std::min(TE, te_request);
+    TE = std::max(1, std::min(TE, NE));
+    const long budget = (long)(mfmak::kWinBudget / 8);
+    *out = taps;
+    out->nchunk = 0;
+    groups->n = 0;
+    int t = 0;
+    long win_max = 0;
+    while (t < taps.n) {
+        int u = t + 1;
+        while (u < taps.n && (long)(TE + taps.s[t] - taps.s[u]) * NN <= budget)
+            ++u;
+        groups->gb[out->nchunk] = groups->n;
+        for (int g = t; g < u; g += mfmak::kGS)
+            groups->t0[groups->n++] = g;
+        out->cb[out->nchunk++] = t;
+        win_max = std::max(win_max, (long)(TE + taps.s[t] - taps.s[u - 1]) * NN);
+        t = u;
+    }
+    out->cb[out->nchunk] = taps.n;
+    groups->gb[out->nchunk] = groups->n;
+    TileGeom g;
+    g.TE = TE;
+    g.n_etiles = (NE + TE - 1) / TE;
+    g.lds_win = (int)win_max;
+    g.lds_scr = kN3D * TE * NN;
+    g.lds_bytes = std::max((size_t)g.lds_win * 8, (size_t)g.lds_scr * 16) +
+                  (size_t)kN3D * NN * sizeof(double);
+    return g;
+}
+
+size_t mfma_afrag_bytes(int, int NA, int NB, int Nqz, const GroupTable &g)
+{
+    return (size_t)NA * NB * Nqz * g.n * 64 * 32;
+}
+
+}  // namespace sse

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "sse.h"
@@ -9,6 +10,24 @@
 namespace sse {
 
 constexpr int kMaxTaps = 128;
+
+// Binary64 tiled kernel: 256 threads, 4 positions each; two workgroups share
+// one CU's 160 KiB of LDS.
+namespace fp64k {
+constexpr int kBlock = 256;
+constexpr int kR = 4;
+constexpr int kPmax = kBlock * kR;
+constexpr size_t kLdsBudget = 78 * 1024;
+}  // namespace fp64k
+
+// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.
+namespace mfmak {
+constexpr int kBlock = 256;
+constexpr int kNT = 4;
+constexpr int kPwg = (kBlock / 64) * kNT * 32;
+constexpr int kGS = 8;
+constexpr size_t kWinBudget = 64 * 1024;
+}  // namespace mfmak
 constexpr int kMaxNorb = 30;
 constexpr int kMaxNB = 50;
 constexpr int kN3D = 3;

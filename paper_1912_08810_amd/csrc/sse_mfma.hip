@@ -31,13 +31,12 @@ namespace sse {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kNT = 4;                      // 32-column tiles per wave
-constexpr int kPwg = kWaves * kNT * 32;     // output positions per workgroup
-constexpr int kGS = 8;                      // taps per group
-constexpr size_t kWinBudget = 64 * 1024;    // LDS bytes for the G window
-constexpr int kSR = kPwg / kBlock;          // sandwich positions per thread
+constexpr int kBlock = mfmak::kBlock;
+constexpr int kNT = mfmak::kNT;               // 32-column tiles per wave
+constexpr int kPwg = mfmak::kPwg;             // output positions per workgroup
+constexpr int kGS = mfmak::kGS;               // taps per group
+constexpr size_t kWinBudget = mfmak::kWinBudget;
+constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -398,58 +397,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLa
 
 }  // namespace
 
-TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out,
-                       GroupTable *groups)
-{
-    const int NN = Norb * Norb;
-    int TE = kPwg / NN;
-    if (te_request > 0)
-        TE = std::min(TE, te_request);
-    TE = std::max(1, std::min(TE, NE));
-    const long budget = (long)(kWinBudget / 8);
-    *out = taps;
-    out->nchunk = 0;
-    groups->n = 0;
-    int t = 0;
-    long win_max = 0;
-    while (t < taps.n) {
-        int u = t + 1;
-        while (u < taps.n && (long)(TE + taps.s[t] - taps.s[u]) * NN <= budget)
-            ++u;
-        groups->gb[out->nchunk] = groups->n;
-        for (int g = t; g < u; g += kGS)
-            groups->t0[groups->n++] = g;
-        out->cb[out->nchunk++] = t;
-        win_max = std::max(win_max, (long)(TE + taps.s[t] - taps.s[u - 1]) * NN);
-        t = u;
-    }
-    out->cb[out->nchunk] = taps.n;
-    groups->gb[out->nchunk] = groups->n;
-    TileGeom g;
-    g.TE = TE;
-    g.n_etiles = (NE + TE - 1) / TE;
-    g.lds_win = (int)win_max;
-    g.lds_scr = kN3D * TE * NN;
-    g.lds_bytes = std::max((size_t)g.lds_win * 8, (size_t)g.lds_scr * 16) +
-                  (size_t)kN3D * NN * sizeof(double);
-    return g;
-}
-
-size_t mfma_afrag_bytes(int, int NA, int NB, int Nqz, const GroupTable &g)
-{
-    return (size_t)NA * NB * Nqz * g.n * 64 * 32;
-}
-
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s)
 {
     const int64_t n = (int64_t)p.NA * p.NB * p.Nqz * p.groups.n * 64;
     const int64_t nb = (n + 255) / 256;
     if (nb > 0x7fffffffLL)
         return hipErrorInvalidConfiguration;
-    if (prec == SSE_BF16X3)
+    if (prec == SSE_BF16X3) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_prep_afrag<SSE_BF16X3>, dim3((unsigned)nb), dim3(256), 0, s, p);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_prep_afrag<SSE_FP32>, dim3((unsigned)nb), dim3(256), 0, s, p);
+    }
     return hipGetLastError();
 }
 
@@ -467,12 +427,15 @@ hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, siz
             return e;
         attr_set[which] = true;
     }
-    if (prec == SSE_BF16X3)
+    if (prec == SSE_BF16X3) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma_persistent<SSE_BF16X3>, dim3(grid), dim3(kBlock), lds_bytes,
                            s, bl);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma_persistent<SSE_FP32>, dim3(grid), dim3(kBlock), lds_bytes, s,
                            bl);
+    }
     return hipGetLastError();
 }
 
@@ -493,12 +456,15 @@ hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStrea
             return e;
         attr_set[which] = true;
     }
-    if (prec == SSE_BF16X3)
+    if (prec == SSE_BF16X3) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma<SSE_BF16X3>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes,
                            s, p);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma<SSE_FP32>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s,
                            p);
+    }
     return hipGetLastError();
 }
 

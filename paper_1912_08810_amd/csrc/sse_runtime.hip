@@ -692,8 +692,12 @@ static sse_status finish_ticket(uint64_t ticket, bool block)
         tk = it->second;
     }
     hipError_t e = block ? hipEventSynchronize(tk.ev) : hipEventQuery(tk.ev);
-    if (e == hipErrorNotReady)
+    if (e == hipErrorNotReady) {
+        // HIP records the query's "not ready" as the thread's last error; clear it so
+        // the next launch check (ours or the caller's) does not read it as a failure.
+        (void)hipGetLastError();
         return SSE_PENDING;
+    }
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tickets.find(ticket);

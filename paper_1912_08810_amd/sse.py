@@ -41,10 +41,27 @@ class SSEError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < 10 else status}: {text}")
 
 
+def hip_runtimes_mapped():
+    """Distinct HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # Device memory and streams come from PyTorch, whose wheel carries its own HIP
+    # runtime.  Load it first so libsse binds to that same runtime: with two HIP
+    # runtimes in one process, a torch stream handle is a foreign object to ours.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    rts = hip_runtimes_mapped()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are loaded in this process (" + ", ".join(rts) +
+                          "); import torch before any other HIP library")
     c = ctypes
     vp = c.c_void_p
     L.sse_plan.argtypes = [c.POINTER(sse_desc), vp, c.POINTER(vp), c.POINTER(c.c_size_t)]

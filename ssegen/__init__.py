@@ -83,7 +83,13 @@ def _devlib():
     if _dev is None:
         if not os.path.exists(DEVICE_LIB):
             raise RuntimeError("libssegen_device.so is not built (run __graft_entry__.build())")
+        # bind to the HIP runtime PyTorch carries (it supplies memory and streams)
+        import torch  # noqa: F401
         L = ctypes.CDLL(DEVICE_LIB)
+        with open("/proc/self/maps") as fh:
+            rts = sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+        if len(rts) > 1:
+            raise RuntimeError("two HIP runtimes are loaded in this process: " + ", ".join(rts))
         c = ctypes
         L.ssegen_dev_fill_dH.argtypes = [c.c_uint64, c.c_int64, c.c_void_p, c.c_void_p]
         L.ssegen_dev_fill_G.argtypes = [c.c_uint64, c.c_int, c.c_int, c.c_int64, c.c_int, c.c_int,

@@ -17,7 +17,7 @@ class DeviceProblem:
     """Seeded device tensors of one problem (all components)."""
 
     def __init__(self, prob: configs.Problem, seed: int, ncomp: int = 1, fp32: bool = False,
-                 scaled: bool = False, neigh=None):
+                 scaled: bool = False, neigh=None, sync: bool = True):
         torch = torch_mod()
         self.prob, self.seed, self.ncomp, self.fp32, self.scaled = prob, seed, ncomp, fp32, scaled
         p = prob
@@ -39,7 +39,8 @@ class DeviceProblem:
                               self.D.data_ptr() + c * p.d_elems() * 2 * esz, fp32=fp32,
                               stream=stream)
         self.Sigma = torch.full_like(self.G, float("nan"))
-        torch.cuda.synchronize()
+        if sync:
+            torch.cuda.synchronize()
 
     def sigma_host(self, comp: int) -> np.ndarray:
         p = self.prob

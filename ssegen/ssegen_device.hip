@@ -88,6 +88,7 @@ extern "C" {
 
 int ssegen_dev_fill_dH(uint64_t seed, int64_t n, double *out, void *stream)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_fill_dH, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, seed, n,
                        out);
     return (int)hipGetLastError();
@@ -98,14 +99,17 @@ int ssegen_dev_fill_G(uint64_t seed, int comp, int Norb, int64_t nblk, int scale
                       void *out, void *stream)
 {
     const int64_t n = nblk * Norb * Norb;
-    if (fp32)
+    if (fp32) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_fill_antiherm<float>, dim3(grid_for(n, 256)), dim3(256), 0,
                            (hipStream_t)stream, seed, (uint32_t)(SSEGEN_S_G + comp),
                            (uint32_t)(SSEGEN_S_GSCALE + comp), scaled, Norb, nblk, (float *)out);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_fill_antiherm<double>, dim3(grid_for(n, 256)), dim3(256), 0,
                            (hipStream_t)stream, seed, (uint32_t)(SSEGEN_S_G + comp),
                            (uint32_t)(SSEGEN_S_GSCALE + comp), scaled, Norb, nblk, (double *)out);
+    }
     return (int)hipGetLastError();
 }
 
@@ -114,14 +118,17 @@ int ssegen_dev_fill_D(uint64_t seed, int comp, int N3D, int64_t nblk, int fp32, 
                       void *stream)
 {
     const int64_t n = nblk * N3D * N3D;
-    if (fp32)
+    if (fp32) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_fill_antiherm<float>, dim3(grid_for(n, 256)), dim3(256), 0,
                            (hipStream_t)stream, seed, (uint32_t)(SSEGEN_S_D + comp), 0u, 0, N3D,
                            nblk, (float *)out);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_fill_antiherm<double>, dim3(grid_for(n, 256)), dim3(256), 0,
                            (hipStream_t)stream, seed, (uint32_t)(SSEGEN_S_D + comp), 0u, 0, N3D,
                            nblk, (double *)out);
+    }
     return (int)hipGetLastError();
 }
 
@@ -134,12 +141,15 @@ int ssegen_dev_perturb(uint64_t seed, int iteration, uint32_t stream_word, int n
     const int64_t nwg = (nblk + 3) / 4;
     if (nwg > 0x7fffffff)
         return (int)hipErrorInvalidValue;
-    if (fp32)
+    if (fp32) {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_perturb<float>, dim3((unsigned)nwg), dim3(256), 0,
                            (hipStream_t)stream, seed, st, n_side, nblk, (float *)data);
-    else
+    } else {
+        (void)hipGetLastError();
         hipLaunchKernelGGL(k_perturb<double>, dim3((unsigned)nwg), dim3(256), 0,
                            (hipStream_t)stream, seed, st, n_side, nblk, (double *)data);
+    }
     return (int)hipGetLastError();
 }
 

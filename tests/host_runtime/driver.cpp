@@ -1,0 +1,51 @@
+// Host-side runtime test: plans, submissions, sampled-check tickets and batch
+// plans through the C ABI with stand-in launchers.  Exits non-zero on failure.
+#include "sse.h"
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+int main() {
+  sse_desc d{}; d.NA = 30; d.NB = 4; d.Norb = 10; d.N3D = 3; d.Nkz = 3; d.Nqz = 3; d.NE = 41; d.Nw = 8;
+  d.ncomp = 2; d.prec = SSE_BF16X3; d.alpha_re = 0; d.alpha_im = 1;
+  int32_t sh[8] = {1,2,3,4,5,6,7,8};
+  sse_plan_t p, pf; size_t ws, wsf;
+  if (sse_plan(&d, sh, &p, &ws)) { printf("plan: %s\n", sse_last_error()); return 1; }
+  d.prec = SSE_FP64C64; sse_plan(&d, sh, &pf, &wsf);
+  std::vector<char> W(ws + 4096), C(256 + 16 * 64 * 2 + 64);
+  std::vector<int32_t> neigh(120), blocks(64 * 3);
+  std::vector<double> dH(1), G(1), D(1), S(1);
+  sse_args a{neigh.data(), dH.data(), G.data(), D.data(), S.data()};
+  for (int it = 0; it < 200; ++it) {
+    uint64_t t1, t2, t3;
+    if (sse_submit(p, &a, W.data(), ws, nullptr, &t1)) { printf("submit: %s\n", sse_last_error()); return 1; }
+    double rel[2] = {-1, -1};
+    if (sse_check_submit(p, &a, blocks.data(), 64, 1e-5, rel, C.data(), C.size(), nullptr, &t2)) { printf("check: %s\n", sse_last_error()); return 1; }
+    if (sse_submit(pf, &a, W.data(), ws, nullptr, &t3)) return 1;
+    int s1, s3, s2 = sse_wait(t2);
+    while ((s1 = sse_poll(t1)) == SSE_PENDING) {}
+    while ((s3 = sse_poll(t3)) == SSE_PENDING) {}
+    if (s1 || s2 || s3 || rel[0] != 1e-6) { printf("it %d: %d %d %d rel %g\n", it, s1, s2, s3, rel[0]); return 1; }
+  }
+  sse_plan_t p2; size_t ws2; d.prec = SSE_BF16X3; sse_plan(&d, sh, &p2, &ws2);
+  sse_plan_destroy(p); sse_plan_destroy(pf);
+  // batch plan path
+  sse_desc ds[3] = {d, d, d}; for (auto &x : ds) { x.prec = SSE_BF16X3; x.ncomp = 1; }
+  ds[1].NA = 17; ds[2].NE = 77; ds[2].Nw = 5;
+  const int32_t *shs[3] = {sh, sh, sh};
+  sse_plan_t pb; size_t wsb;
+  if (sse_plan_batch(ds, shs, 3, &pb, &wsb)) { printf("batch: %s\n", sse_last_error()); return 1; }
+  std::vector<char> WB(wsb);
+  sse_args aa[3] = {a, a, a};
+  uint64_t tb; if (sse_submit(pb, aa, WB.data(), wsb, nullptr, &tb)) { printf("bsubmit %s\n", sse_last_error()); return 1; }
+  printf("batch poll %d\n", sse_wait(tb));
+  sse_plan_destroy(pb);
+  {
+    uint64_t ta, tb2;
+    if (sse_submit(p2, &a, W.data(), ws, nullptr, &ta)) return 2;
+    if (sse_poll(ta) != SSE_PENDING) return 3;
+    if (sse_submit(p2, &a, W.data(), ws, nullptr, &tb2)) { printf("submit after a pending poll: %s\n", sse_last_error()); return 4; }
+    sse_wait(ta); sse_wait(tb2);
+  }
+  printf("OK\n");
+  return 0;
+}

@@ -1,0 +1,16 @@
+// Stand-in kernel launchers for the host-side runtime test.  They behave like
+// the real wrappers towards the runtime: the status word is cleared, the check
+// sums get known values (|diff|^2 = 1e-12, |ref|^2 = 1), and every launch
+// reports hipGetLastError() as the real launches do.
+#include "sse_internal.h"
+namespace sse {
+hipError_t fp64_launch(const Fp64Params &, bool, size_t, hipStream_t) { return hipSuccess; }
+hipError_t fp64_persistent_launch(const BatchLaunch &, bool, int, size_t, hipStream_t) { return hipSuccess; }
+hipError_t mfma_prep_launch(int, const MfmaPrepParams &, hipStream_t) { return hipSuccess; }
+hipError_t mfma_launch(int, const MfmaParams &, size_t, hipStream_t) { return hipSuccess; }
+hipError_t mfma_persistent_launch(int, const BatchLaunch &, int, size_t, hipStream_t) { return hipSuccess; }
+hipError_t launch_clear_status(uint32_t *s, hipStream_t) { *s = 0; return hipGetLastError(); }
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t) { for (int i = 0; i < n; ++i) p[i] = 0; return hipSuccess; }
+hipError_t launch_validate_neigh(const int32_t *, int64_t, int32_t, uint32_t *, hipStream_t) { return hipSuccess; }
+hipError_t check_launch(const CheckParams &p, double *out, hipStream_t) { out[0] = 1e-12; out[1] = 1.0; return hipSuccess; }
+}

@@ -76,3 +76,30 @@ def test_sampled_check_catches_a_corrupted_result_and_bad_blocks():
     bad[1, 1] = dp.prob.NE  # energy out of range
     ct = sse.sse_check_submit(plan, item, bad, 1.0, ws, torch.cuda.current_stream())
     assert sse.sse_wait(ct.ticket, check=False) == sse.ERR_ARG
+
+
+def test_pending_poll_then_more_launches():
+    """Regression: a poll that finds the submission still running must not make
+    the next launch (the library's, the generator's or torch's) report an error."""
+    import torch
+    import ssegen
+    sse = _sse()
+    prob = configs.Problem(NA=256, NB=4, Norb=10, Nkz=5, Nqz=5, NE=300, Nw=20)
+    dp = gu.DeviceProblem(prob, 61)
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw)
+    plan = sse.sse_plan(desc, prob.shifts())
+    ws = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+    item = [(dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma)]
+    st = torch.cuda.current_stream()
+    t1 = sse.sse_submit(plan, item, ws, st)
+    saw_pending = sse.sse_poll(t1) == sse.PENDING
+    x = torch.ones(1024, device="cuda")
+    x.add_(1.0)                                     # torch launch
+    ssegen.dev_fill_dH(3, dp.dH.numel(), dp.dH.data_ptr(), st.cuda_stream)  # generator launch
+    sse.sse_wait(t1)
+    t2 = sse.sse_submit(plan, item, ws, st)         # library launch
+    while sse.sse_poll(t2) == sse.PENDING:
+        pass
+    torch.cuda.synchronize()
+    assert float(x[0]) == 2.0
+    print(f"  first poll pending: {saw_pending}", flush=True)

@@ -1,0 +1,28 @@
+"""The runtime's host code (plans, submission, tickets, check bookkeeping,
+batch tables) under AddressSanitizer and UBSan, on the CPU: it is built with
+g++ from the library's own sources against a stand-in HIP header and stub
+launchers (tests/host_runtime/), and driven through the C ABI.  Includes the
+regression test for polling: a pending sse_poll must not make the next
+submission report a launch failure."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+H = os.path.join(ROOT, "tests", "host_runtime")
+CSRC = os.path.join(ROOT, "paper_1912_08810_amd", "csrc")
+
+
+def test_runtime_host_code_under_sanitizers(tmp_path):
+    exe = os.path.join(tmp_path, "runtime_host_test")
+    cmd = ["g++", "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined",
+           "-fno-omit-frame-pointer", "-x", "c++", "-I", H, "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, os.path.join(CSRC, "sse_runtime.hip"), os.path.join(CSRC, "sse_geometry.hip"),
+           os.path.join(H, "launch_stubs.cpp"), os.path.join(H, "driver.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])

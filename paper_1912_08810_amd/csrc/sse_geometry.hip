@@ -81,4 +81,13 @@ size_t mfma_afrag_bytes(int, int NA, int NB, int Nqz, const GroupTable &g)
     return (size_t)NA * NB * Nqz * g.n * 64 * 32;
 }
 
+size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int Norb,
+                      const GroupTable &g)
+{
+    size_t b = (mfma_afrag_bytes(prec, NA, NB, Nqz, g) + 255) & ~(size_t)255;
+    if (prec == SSE_BF16X3)
+        b += (size_t)Nkz * NE * NA * Norb * Norb * 8;
+    return b;
+}
+
 }  // namespace sse

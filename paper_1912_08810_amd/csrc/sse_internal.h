@@ -137,7 +137,7 @@ struct GroupTable {
 struct MfmaParams {
     const int32_t *neigh;
     const double *dH;
-    const float2 *G;
+    const void *G;      // 8-byte elements: complex64 (fp32) or pre-split bf16 pairs (bf16x3)
     const void *afrag;  // per (a, b, q, group, lane) A-operand fragments (prep kernel)
     float2 *Sigma;
     int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
@@ -194,7 +194,12 @@ hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, siz
 TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
                        TapTable *taps_out, GroupTable *groups_out);
 size_t mfma_afrag_bytes(int prec, int NA, int NB, int Nqz, const GroupTable &g);
+// Workspace of one MFMA instance: A fragments, then (bf16x3) the split copy of G.
+size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int Norb,
+                      const GroupTable &g);
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s);
+// bf16x3: n complex64 values of G -> n (hi, lo) bf16 pairs of 8 bytes each
+hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t s);
 hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStream_t s);
 hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,
                                   hipStream_t s);

@@ -174,6 +174,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
 
     const size_t strideE = (size_t)p.NA * NN;
     const uint4 *afrag = reinterpret_cast<const uint4 *>(ptr.aux);
+    // staging walk: element idx = tid + 256 it is (energy ew, channel cc)
+    const int st_e = kBlock / NN, st_c = kBlock - (kBlock / NN) * NN;
+    const int ew0 = tid / NN, cc0 = tid - (tid / NN) * NN;
 
     for (int b = 0; b < p.NB; ++b) {
         const int f = ptr.neigh[(size_t)a * p.NB + b];
@@ -190,8 +193,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
             int kk = k - q;
             if (kk < 0)
                 kk += p.Nkz;
-            const float2 *Gk =
-                (const float2 *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
+            // G rows as 8-byte window elements: float2 (fp32) or the pre-split
+            // bf16 (hi, lo) pairs written by k_split_g (bf16x3)
+            const uint2 *Gk = (const uint2 *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
             const uint4 *aq = afrag + ((((size_t)a * p.NB + b) * p.Nqz + q) * p.groups.n) * 128;
             for (int c = 0; c < p.taps.nchunk; ++c) {
                 const int t1c = p.taps.cb[c + 1];
@@ -199,23 +203,21 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
                 const int wn = (te + smax - smin) * NN;
                 const int ebase = e0 - smax;
                 __syncthreads();
-                for (int idx = tid; idx < wn; idx += kBlock) {
-                    const int ew = idx / NN;
-                    const int cc = idx - ew * NN;
-                    const int e = ebase + ew;
-                    float2 v = make_float2(0.0f, 0.0f);
-                    if (e >= 0 && e < p.NE)
-                        v = Gk[(size_t)e * strideE + cc];
-                    uint2 w;
-                    if (PREC == SSE_BF16X3) {
-                        uint32_t rh, rl, ih, il;
-                        split_bf16(v.x, rh, rl);
-                        split_bf16(v.y, ih, il);
-                        w = make_uint2(rh | ih << 16, rl | il << 16);
-                    } else {
-                        w = make_uint2(__float_as_uint(v.x), __float_as_uint(v.y));
+                {
+                    int ew = ew0, cc = cc0;
+                    for (int idx = tid; idx < wn; idx += kBlock) {
+                        const int e = ebase + ew;
+                        uint2 w = make_uint2(0u, 0u);
+                        if (e >= 0 && e < p.NE)
+                            w = Gk[(size_t)e * strideE + cc];
+                        win[idx] = w;
+                        cc += st_c;
+                        ew += st_e;
+                        if (cc >= NN) {
+                            cc -= NN;
+                            ++ew;
+                        }
                     }
-                    win[idx] = w;
                 }
                 __syncthreads();
 
@@ -359,6 +361,19 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
     }
 }
 
+// bf16x3: every complex64 value of G as (re_hi | im_hi << 16, re_lo | im_lo << 16).
+__global__ void k_split_g(const float2 *__restrict__ G, uint2 *__restrict__ out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 v = G[i];
+        uint32_t rh, rl, ih, il;
+        split_bf16(v.x, rh, rl);
+        split_bf16(v.y, ih, il);
+        out[i] = make_uint2(rh | ih << 16, rl | il << 16);
+    }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
 {
@@ -368,7 +383,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
     L /= p.Nkz;
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
-    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
+    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};  // G: 8-byte elements
     mfma_tile<PREC>(p, ptr, a, k, et, smem);
 }
 
@@ -396,6 +411,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLa
 }
 
 }  // namespace
+
+hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t s)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > 65536)
+        g = 65536;
+    if (g < 1)
+        g = 1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_split_g, dim3((unsigned)g), dim3(256), 0, s, G, (uint2 *)out, n);
+    return hipGetLastError();
+}
 
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s)
 {

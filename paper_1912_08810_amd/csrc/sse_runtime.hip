@@ -44,7 +44,7 @@ struct Instance {
     TapTable taps;      // sorted and chunked for this instance's tile geometry
     GroupTable groups;  // MFMA path: tap groups per chunk
     TileGeom geom;
-    size_t afrag_bytes = 0;  // MFMA path: workspace for the A-operand fragments
+    size_t afrag_bytes = 0;  // MFMA path: workspace for the A fragments (+ split G, bf16x3)
 };
 
 constexpr size_t kStatusBytes = 256;  // status word region at the start of the workspace
@@ -167,7 +167,8 @@ sse_status build_instance(const sse_desc *d, const int32_t *w_shift, Instance *o
                         "sse_plan: the complex64 (MFMA) precisions support Norb <= 22 (got %d)",
                         d->Norb);
         out->geom = mfma_geometry(d->Norb, d->NE, t, te_request, &out->taps, &out->groups);
-        out->afrag_bytes = mfma_afrag_bytes(d->prec, d->NA, d->NB, d->Nqz, out->groups);
+        out->afrag_bytes = mfma_aux_bytes(d->prec, d->NA, d->NB, d->Nqz, d->Nkz, d->NE, d->Norb,
+                                          out->groups);
     }
     const int64_t nwg = (int64_t)out->geom.n_etiles * d->Nkz * d->NA;
     if (nwg > 0x7fffffffLL)
@@ -233,10 +234,20 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
             e = mfma_prep_launch(d.prec, pp, s);
             if (e != hipSuccess)
                 return hip_fail(e, "MFMA prep launch");
+            const void *Gm = G;
+            if (d.prec == SSE_BF16X3) {
+                char *split = (char *)wsfree +
+                              ((mfma_afrag_bytes(d.prec, d.NA, d.NB, d.Nqz, I.groups) + 255) &
+                               ~(size_t)255);
+                e = mfma_split_launch((const float2 *)G, split, (int64_t)g_elems, s);
+                if (e != hipSuccess)
+                    return hip_fail(e, "G split launch");
+                Gm = split;
+            }
             MfmaParams p{};
             p.neigh = a.neigh;
             p.dH = a.dH;
-            p.G = (const float2 *)G;
+            p.G = Gm;
             p.afrag = wsfree;
             p.Sigma = (float2 *)S;
             p.NA = d.NA;
@@ -424,6 +435,15 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
             bl.ptr[t].D = (const char *)args[t].Dt + c * d_elems * eb;
             bl.ptr[t].Sigma = (char *)args[t].Sigma + c * g_elems * eb;
             bl.ptr[t].aux = ws + P->afrag_off[t];
+            if (d.prec == SSE_BF16X3) {
+                char *split = ws + P->afrag_off[t] +
+                              ((mfma_afrag_bytes(d.prec, d.NA, d.NB, d.Nqz, P->inst[t].groups) +
+                                255) & ~(size_t)255);
+                e = mfma_split_launch((const float2 *)bl.ptr[t].G, split, (int64_t)g_elems, s);
+                if (e != hipSuccess)
+                    return hip_fail(e, "G split launch");
+                bl.ptr[t].G = split;
+            }
             if (!fp64_arith(d.prec)) {
                 MfmaPrepParams pp{};
                 pp.D = (const float2 *)bl.ptr[t].D;

@@ -65,7 +65,8 @@ def job_bytes(prob: configs.Problem, ncomp: int = 2, nsample: int = 64) -> int:
     dh = prob.NA * prob.NB * prob.N3D * prob.NN * 8
     groups = sum(math.ceil(n / 8) for n in [prob.Nw])  # one chunk at these sizes
     afrag = prob.NA * prob.NB * prob.Nqz * groups * 64 * 32
-    return 2 * g + d + dh + afrag + 256 + sse.check_workspace_bytes(nsample, ncomp) + \
+    split = prob.g_elems() * 8  # bf16 (hi, lo) copy of one component's G
+    return 2 * g + d + dh + afrag + split + 512 + sse.check_workspace_bytes(nsample, ncomp) + \
         prob.NA * prob.NB * 4
 
 

@@ -7,6 +7,7 @@ namespace sse {
 hipError_t fp64_launch(const Fp64Params &, bool, size_t, hipStream_t) { return hipSuccess; }
 hipError_t fp64_persistent_launch(const BatchLaunch &, bool, int, size_t, hipStream_t) { return hipSuccess; }
 hipError_t mfma_prep_launch(int, const MfmaPrepParams &, hipStream_t) { return hipSuccess; }
+hipError_t mfma_split_launch(const float2 *, void *, int64_t, hipStream_t) { return hipGetLastError(); }
 hipError_t mfma_launch(int, const MfmaParams &, size_t, hipStream_t) { return hipSuccess; }
 hipError_t mfma_persistent_launch(int, const BatchLaunch &, int, size_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_clear_status(uint32_t *s, hipStream_t) { *s = 0; return hipGetLastError(); }

@@ -66,14 +66,16 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double x, double y
     return make_float2((float)x, (float)y);
 }
 
-// One output tile: energies [et TE, et TE + TE) of (k, a).  p supplies the
-// problem's sizes and tap table (it may live in global memory), ptr its tensors.
+// One output tile: energies [et TE, et TE + TE) of (k, a).  pp supplies the
+// problem's sizes and tap table (a kernel argument or a batch table in global
+// memory), ptr its tensors.
 // T is the storage type of G, D~ and Sigma (complex128, or complex64 promoted to
 // binary64 on load); all arithmetic is binary64.
 template <typename T>
-__device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs &ptr, int a, int k,
-                                          int et, double2 *lds)
+__device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const TensorPtrs &ptr, int a,
+                                          int k, int et, double2 *lds)
 {
+    const auto &p = *pp;
     double *ldsA = reinterpret_cast<double *>(lds + p.lds_win);
     const int e0 = et * p.TE;
     const int te = min(p.TE, p.NE - e0);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs 
     const int ew0 = tid / NN, cc0 = tid - (tid / NN) * NN;
 
     for (int b = 0; b < p.NB; ++b) {
-        const int f = ptr.neigh[(size_t)a * p.NB + b];
+        const int f = ro(ptr.neigh)[(size_t)a * p.NB + b];
         if ((unsigned)f >= (unsigned)p.NA)
             continue;  // invalid neighbour: reported by the validation kernel
 
@@ -112,13 +114,13 @@ __device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs 
                 ai[r][x] = 0.0;
             }
 
-        const T *Dab = (const T *)ptr.D + ((size_t)a * p.NB + b) * kNF;
+        const_ptr<T> Dab = ro((const T *)ptr.D) + ((size_t)a * p.NB + b) * kNF;
         for (int q = 0; q < p.Nqz; ++q) {
             int kk = k - q;
             if (kk < 0)
                 kk += p.Nkz;
             const T *Gk = (const T *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
-            const T *Dq = Dab + (size_t)q * p.Nw * strideD;
+            const_ptr<T> Dq = Dab + (size_t)q * p.Nw * strideD;
             for (int c = 0; c < p.taps.nchunk; ++c) {
                 const int t0 = p.taps.cb[c], t1 = p.taps.cb[c + 1];
                 const int smax = p.taps.s[t0], smin = p.taps.s[t1 - 1];
@@ -148,8 +150,8 @@ __device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs 
                 int t = t0;
                 constexpr int kPair = sizeof(T) == sizeof(double2) ? 1 : 0;
                 for (; kPair && t + 1 < t1; t += 2) {
-                    const T *dpa = Dq + (size_t)p.taps.w[t] * strideD;
-                    const T *dpb = Dq + (size_t)p.taps.w[t + 1] * strideD;
+                    const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;
+                    const_ptr<T> dpb = Dq + (size_t)p.taps.w[t + 1] * strideD;
                     double2 da[kNF], db[kNF];
 #pragma unroll
                     for (int x = 0; x < kNF; ++x) {
@@ -171,7 +173,7 @@ __device__ __forceinline__ void fp64_tile(const Fp64Params &p, const TensorPtrs 
                     }
                 }
                 for (; t < t1; ++t) {
-                    const T *dpa = Dq + (size_t)p.taps.w[t] * strideD;
+                    const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;
                     double2 da[kNF];
 #pragma unroll
                     for (int x = 0; x < kNF; ++x)
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
     const TensorPtrs ptr{p.neigh, p.dH, p.G, p.D, p.Sigma};
-    fp64_tile<T>(p, ptr, a, k, et, lds);
+    fp64_tile<T>(ro(&p), ptr, a, k, et, lds);
 }
 
 // Persistent form: a fixed grid pulls tiles from the batch's work queues
@@ -307,8 +309,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLa
         __syncthreads();
         if (inst < 0)
             break;
-        const Fp64Params &p = reinterpret_cast<const Fp64Params *>(bl.params)[inst];
-        fp64_tile<T>(p, bl.ptr[inst], a, k, et, lds);
+        fp64_tile<T>(ro(reinterpret_cast<const Fp64Params *>(bl.params)) + inst, bl.ptr[inst], a,
+                     k, et, lds);
     }
 }
 

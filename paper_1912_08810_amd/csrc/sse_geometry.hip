@@ -47,7 +47,8 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     if (te_request > 0)
         TE = std::min(TE, te_request);
     TE = std::max(1, std::min(TE, NE));
-    const long budget = (long)(mfmak::kWinBudget / 8);
+    // A plane holds the window rows plus the reach of the columns past the
+    // tile's last position: kPwg + (shift spread of the chunk) NN words.
     *out = taps;
     out->nchunk = 0;
     groups->n = 0;
@@ -55,7 +56,8 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     long win_max = 0;
     while (t < taps.n) {
         int u = t + 1;
-        while (u < taps.n && (long)(TE + taps.s[t] - taps.s[u]) * NN <= budget)
+        while (u < taps.n &&
+               mfmak::kPwg + (long)(taps.s[t] - taps.s[u]) * NN <= mfmak::kPlaneWords)
             ++u;
         groups->gb[out->nchunk] = groups->n;
         for (int g = t; g < u; g += mfmak::kGS)
@@ -71,8 +73,7 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     g.n_etiles = (NE + TE - 1) / TE;
     g.lds_win = (int)win_max;
     g.lds_scr = kN3D * TE * NN;
-    g.lds_bytes = std::max((size_t)g.lds_win * 8, (size_t)g.lds_scr * 16) +
-                  (size_t)kN3D * NN * sizeof(double);
+    g.lds_bytes = 2 * mfmak::kPlaneBytes + (size_t)kN3D * NN * sizeof(double);
     return g;
 }
 

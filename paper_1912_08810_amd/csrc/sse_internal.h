@@ -11,6 +11,25 @@ namespace sse {
 
 constexpr int kMaxTaps = 128;
 
+// Data the kernels only read (parameter tables, D~, dH, the neighbour table)
+// is addressed through the constant address space.  Nothing in a launch writes
+// it, so wave-uniform reads may use scalar loads also after the kernel has
+// stored results (a persistent kernel stores a tile, then reads the next
+// tile's parameters).  The host compilation pass only type-checks kernel
+// bodies, and there the alias is a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename X>
+using const_ptr = const __attribute__((address_space(4))) X *;
+#else
+template <typename X>
+using const_ptr = const X *;
+#endif
+template <typename X>
+__device__ __forceinline__ const_ptr<X> ro(const X *p)
+{
+    return (const_ptr<X>)p;
+}
+
 // Binary64 tiled kernel: 256 threads, 4 positions each; two workgroups share
 // one CU's 160 KiB of LDS.
 namespace fp64k {
@@ -20,13 +39,16 @@ constexpr int kPmax = kBlock * kR;
 constexpr size_t kLdsBudget = 78 * 1024;
 }  // namespace fp64k
 
-// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.
+// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.  The G
+// window sits in LDS as two planes of 32-bit words at fixed offsets (bf16 hi
+// and lo pairs, or fp32 re and im), followed by the dH rows.
 namespace mfmak {
 constexpr int kBlock = 256;
 constexpr int kNT = 4;
 constexpr int kPwg = (kBlock / 64) * kNT * 32;
 constexpr int kGS = 8;
-constexpr size_t kWinBudget = 64 * 1024;
+constexpr int kPlaneWords = 8192;
+constexpr size_t kPlaneBytes = (size_t)kPlaneWords * 4;
 }  // namespace mfmak
 constexpr int kMaxNorb = 30;
 constexpr int kMaxNB = 50;

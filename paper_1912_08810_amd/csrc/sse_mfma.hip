@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sse_internal.h"
 
@@ -35,7 +36,7 @@ constexpr int kBlock = mfmak::kBlock;
 constexpr int kNT = mfmak::kNT;               // 32-column tiles per wave
 constexpr int kPwg = mfmak::kPwg;             // output positions per workgroup
 constexpr int kGS = mfmak::kGS;               // taps per group
-constexpr size_t kWinBudget = mfmak::kWinBudget;
+constexpr size_t kPlaneBytes = mfmak::kPlaneBytes;
 constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -121,17 +122,58 @@ __global__ void k_prep_afrag(const MfmaPrepParams p)
     }
 }
 
-// One output tile (energies [et TE, et TE + TE) of (k, a)); p supplies sizes and
-// tap/group tables (possibly from global memory), ptr the tensors (aux = A fragments).
-template <int PREC>
-__device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs &ptr, int a, int k,
-                                          int et, unsigned char *smem)
+// Copy window rows [0, nrow) (row r = energy ebase + r of the neighbour's G
+// rows, zero outside [0, NE)) into the two LDS planes: word 0 of each 8-byte
+// element to plane 0, word 1 to plane 1.  Wave wv copies rows wv, wv + 4, ...;
+// a row's address is wave-uniform, so only the column offset is per lane.
+template <typename V>
+__device__ __forceinline__ void stage_rows(const uint2 *Gk, size_t strideE, int NE, int ebase,
+                                           int nrow, int NN, int wv, int lane, uint32_t *P0,
+                                           uint32_t *P1)
 {
-    uint2 *win = reinterpret_cast<uint2 *>(smem);       // G window, 8 bytes per complex
-    double2 *scr = reinterpret_cast<double2 *>(smem);   // sandwich scratch (aliases window)
-    const size_t a_off = ((size_t)p.lds_win * 8 > (size_t)p.lds_scr * 16) ? (size_t)p.lds_win * 8
-                                                                          : (size_t)p.lds_scr * 16;
-    double *ldsA = reinterpret_cast<double *>(smem + a_off);
+    constexpr int kE = sizeof(V) / sizeof(uint2);  // elements per lane load
+    constexpr int kRB = 4;                         // rows in flight per wave
+    const int nv = NN / kE;
+    for (int r0 = wv; r0 < nrow; r0 += 4 * kRB) {
+        for (int c = lane; c < nv; c += 64) {
+            V v[kRB];
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb) {
+                const int r = r0 + 4 * rb;
+                const int e = ebase + r;
+                v[rb] = V{};
+                if (r < nrow && e >= 0 && e < NE)
+                    v[rb] = reinterpret_cast<const V *>(Gk + (size_t)e * strideE)[c];
+            }
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb) {
+                const int r = r0 + 4 * rb;
+                if (r >= nrow)
+                    break;
+                if constexpr (kE == 2) {
+                    *reinterpret_cast<uint2 *>(P0 + r * NN + 2 * c) = make_uint2(v[rb].x, v[rb].z);
+                    *reinterpret_cast<uint2 *>(P1 + r * NN + 2 * c) = make_uint2(v[rb].y, v[rb].w);
+                } else {
+                    P0[r * NN + c] = v[rb].x;
+                    P1[r * NN + c] = v[rb].y;
+                }
+            }
+        }
+    }
+}
+
+// One output tile (energies [et TE, et TE + TE) of (k, a)); pp supplies sizes and
+// tap/group tables (a kernel argument or a batch table in global memory), ptr
+// the tensors (aux = A fragments).
+template <int PREC>
+__device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const TensorPtrs &ptr, int a,
+                                          int k, int et, unsigned char *smem)
+{
+    const auto &p = *pp;
+    uint32_t *P0 = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *P1 = reinterpret_cast<uint32_t *>(smem + kPlaneBytes);
+    double2 *scr = reinterpret_cast<double2 *>(smem);   // sandwich scratch (aliases plane 0)
+    double *ldsA = reinterpret_cast<double *>(smem + 2 * kPlaneBytes);
 
     const int e0 = et * p.TE;
     const int te = min(p.TE, p.NE - e0);
@@ -140,17 +182,16 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
     const int Pst = p.TE * NN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
 
-    // MFMA columns of this lane: one output position per tile
-    int pcol[kNT];
+    // MFMA column of this lane in tile t: pos0 + 32 t.  Columns at or past P
+    // read in-plane words (the plane holds kPwg + spread NN words) and their
+    // results are never used: an MFMA column depends on its B column only.
+    const int pos0 = wave * kNT * 32 + (lane & 31);
     bool pval[kNT];
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) {
-        pcol[t] = (wave * kNT + t) * 32 + (lane & 31);
-        pval[t] = pcol[t] < P;
-        if (!pval[t])
-            pcol[t] = 0;
-    }
+    for (int t = 0; t < kNT; ++t)
+        pval[t] = pos0 + 32 * t < P;
     // sandwich positions of this thread
     int spos[kSR], pe[kSR], pm[kSR], pn[kSR];
     bool sval[kSR];
@@ -174,12 +215,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
 
     const size_t strideE = (size_t)p.NA * NN;
     const uint4 *afrag = reinterpret_cast<const uint4 *>(ptr.aux);
-    // staging walk: element idx = tid + 256 it is (energy ew, channel cc)
-    const int st_e = kBlock / NN, st_c = kBlock - (kBlock / NN) * NN;
-    const int ew0 = tid / NN, cc0 = tid - (tid / NN) * NN;
 
     for (int b = 0; b < p.NB; ++b) {
-        const int f = ptr.neigh[(size_t)a * p.NB + b];
+        const int f = ro(ptr.neigh)[(size_t)a * p.NB + b];
         if ((unsigned)f >= (unsigned)p.NA)
             continue;
         double acc[kNT][10];
@@ -200,78 +238,92 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
             for (int c = 0; c < p.taps.nchunk; ++c) {
                 const int t1c = p.taps.cb[c + 1];
                 const int smax = p.taps.s[p.taps.cb[c]], smin = p.taps.s[t1c - 1];
-                const int wn = (te + smax - smin) * NN;
-                const int ebase = e0 - smax;
                 __syncthreads();
-                {
-                    int ew = ew0, cc = cc0;
-                    for (int idx = tid; idx < wn; idx += kBlock) {
-                        const int e = ebase + ew;
-                        uint2 w = make_uint2(0u, 0u);
-                        if (e >= 0 && e < p.NE)
-                            w = Gk[(size_t)e * strideE + cc];
-                        win[idx] = w;
-                        cc += st_c;
-                        ew += st_e;
-                        if (cc >= NN) {
-                            cc -= NN;
-                            ++ew;
-                        }
-                    }
-                }
+                if ((NN & 1) == 0)
+                    stage_rows<uint4>(Gk, strideE, p.NE, e0 - smax, te + smax - smin, NN, wv,
+                                      lane, P0, P1);
+                else
+                    stage_rows<uint2>(Gk, strideE, p.NE, e0 - smax, te + smax - smin, NN, wv,
+                                      lane, P0, P1);
                 __syncthreads();
 
                 f32x16 C[kNT];
-#pragma unroll
-                for (int t = 0; t < kNT; ++t)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v)
-                        C[t][v] = 0.0f;
-
-                for (int g = p.groups.gb[c]; g < p.groups.gb[c + 1]; ++g) {
-                    const uint4 A0 = aq[(size_t)g * 128 + lane * 2];
-                    const uint4 A1 = aq[(size_t)g * 128 + lane * 2 + 1];
+                // one group of kGS taps; the first group of a window starts
+                // from a zero accumulator
+                auto step = [&](int g, const uint4 &A0, const uint4 &A1, auto first) {
+                    constexpr bool kFirst = decltype(first)::value;
                     const int tg = p.groups.t0[g];
-                    if (PREC == SSE_BF16X3) {
-                        int off[4];
+                    if constexpr (PREC == SSE_BF16X3) {
+                        // lanes of half h carry taps tg + 4 h + u, u = 0..3
+                        int idx[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int t = tg + 4 * h + u;
-                            off[u] = t < t1c ? (smax - p.taps.s[t]) * NN : 0;
+                            const int ta = tg + u, tb = tg + 4 + u;
+                            const int oa = ta < t1c ? (smax - p.taps.s[ta]) * NN : 0;
+                            const int ob = tb < t1c ? (smax - p.taps.s[tb]) * NN : 0;
+                            idx[u] = pos0 + (h ? ob : oa);
                         }
                         const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
                         const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
 #pragma unroll
                         for (int t = 0; t < kNT; ++t) {
-                            uint2 w[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                w[u] = win[pcol[t] + off[u]];
-                            const bf16x8 bhi =
-                                __builtin_bit_cast(bf16x8, make_uint4(w[0].x, w[1].x, w[2].x, w[3].x));
-                            const bf16x8 blo =
-                                __builtin_bit_cast(bf16x8, make_uint4(w[0].y, w[1].y, w[2].y, w[3].y));
-                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0, 0);
+                            const uint4 wh = make_uint4(P0[idx[0] + 32 * t], P0[idx[1] + 32 * t],
+                                                        P0[idx[2] + 32 * t], P0[idx[3] + 32 * t]);
+                            const uint4 wl = make_uint4(P1[idx[0] + 32 * t], P1[idx[1] + 32 * t],
+                                                        P1[idx[2] + 32 * t], P1[idx[3] + 32 * t]);
+                            const bf16x8 bhi = __builtin_bit_cast(bf16x8, wh);
+                            const bf16x8 blo = __builtin_bit_cast(bf16x8, wl);
+                            if constexpr (kFirst)
+                                C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, f32x16{}, 0,
+                                                                               0, 0);
+                            else
+                                C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0,
+                                                                               0);
                             C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, C[t], 0, 0, 0);
                             C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, C[t], 0, 0, 0);
                         }
                     } else {
+                        // K = 2 per instruction: lanes of half h carry component h
+                        // (plane h) of tap tg + u
                         const float av[8] = {__uint_as_float(A0.x), __uint_as_float(A0.y),
                                              __uint_as_float(A0.z), __uint_as_float(A0.w),
                                              __uint_as_float(A1.x), __uint_as_float(A1.y),
                                              __uint_as_float(A1.z), __uint_as_float(A1.w)};
-                        const float *winf = reinterpret_cast<const float *>(win);
+                        const float *Ph = reinterpret_cast<const float *>(h ? P1 : P0);
 #pragma unroll
                         for (int u = 0; u < kGS; ++u) {
                             const int t = tg + u;
-                            const int off = t < t1c ? (smax - p.taps.s[t]) * NN : 0;
+                            const int idx = pos0 + (t < t1c ? (smax - p.taps.s[t]) * NN : 0);
 #pragma unroll
                             for (int tt = 0; tt < kNT; ++tt) {
-                                const float bv = winf[2 * (pcol[tt] + off) + h];
-                                C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, C[tt], 0, 0, 0);
+                                const float bv = Ph[idx + 32 * tt];
+                                if (kFirst && u == 0)
+                                    C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, f32x16{},
+                                                                                 0, 0, 0);
+                                else
+                                    C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, C[tt], 0,
+                                                                                 0, 0);
                             }
                         }
                     }
+                };
+                const int g0 = p.groups.gb[c], g1 = p.groups.gb[c + 1];
+                uint4 A0 = aq[(size_t)g0 * 128 + lane * 2];
+                uint4 A1 = aq[(size_t)g0 * 128 + lane * 2 + 1];
+                uint4 N0 = A0, N1 = A1;
+                if (g0 + 1 < g1) {
+                    N0 = aq[(size_t)(g0 + 1) * 128 + lane * 2];
+                    N1 = aq[(size_t)(g0 + 1) * 128 + lane * 2 + 1];
+                }
+                step(g0, A0, A1, std::true_type{});
+                for (int g = g0 + 1; g < g1; ++g) {
+                    A0 = N0;
+                    A1 = N1;
+                    if (g + 1 < g1) {
+                        N0 = aq[(size_t)(g + 1) * 128 + lane * 2];
+                        N1 = aq[(size_t)(g + 1) * 128 + lane * 2 + 1];
+                    }
+                    step(g, A0, A1, std::false_type{});
                 }
                 // fold this window's fp32 partial sums into the binary64 accumulators
 #pragma unroll
@@ -307,7 +359,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams &p, const TensorPtrs 
                     const int row = 8 * (v >> 2) + 4 * h + (v & 3);
                     const int ij = row >> 1;
                     if (ij < kNF && ij / kN3D == i && pval[t])
-                        scr[(ij % kN3D) * Pst + pcol[t]] = make_double2(acc[t][v], acc[t][v + 1]);
+                        scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
+                            make_double2(acc[t][v], acc[t][v + 1]);
                 }
             __syncthreads();
 #pragma unroll
@@ -384,7 +437,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
     const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};  // G: 8-byte elements
-    mfma_tile<PREC>(p, ptr, a, k, et, smem);
+    mfma_tile<PREC>(ro(&p), ptr, a, k, et, smem);
 }
 
 // Persistent form over a batch's work queues (see batch_pull).
@@ -405,8 +458,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLa
         __syncthreads();
         if (inst < 0)
             break;
-        const MfmaParams &p = reinterpret_cast<const MfmaParams *>(bl.params)[inst];
-        mfma_tile<PREC>(p, bl.ptr[inst], a, k, et, smem);
+        mfma_tile<PREC>(ro(reinterpret_cast<const MfmaParams *>(bl.params)) + inst, bl.ptr[inst],
+                        a, k, et, smem);
     }
 }
 
@@ -449,7 +502,7 @@ hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, siz
     const int which = prec == SSE_BF16X3;
     if (!attr_set[which]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kWinBudget + 16 * 1024));
+                                           (int)(2 * kPlaneBytes + 16 * 1024));
         if (e != hipSuccess)
             return e;
         attr_set[which] = true;
@@ -478,7 +531,7 @@ hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStrea
     const int which = prec == SSE_BF16X3;
     if (!attr_set[which]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kWinBudget + 16 * 1024));
+                                           (int)(2 * kPlaneBytes + 16 * 1024));
         if (e != hipSuccess)
             return e;
         attr_set[which] = true;

@@ -68,10 +68,11 @@ struct sse_plan_s {
     int grid = 0;
     ~sse_plan_s()
     {
-        hipFree(d_params);
-        hipFree(d_chunk_inst);
-        hipFree(d_chunk_atom);
-        hipFree(d_chunk_start);
+        // nothing useful can be done with a failure while destroying a plan
+        (void)hipFree(d_params);
+        (void)hipFree(d_chunk_inst);
+        (void)hipFree(d_chunk_atom);
+        (void)hipFree(d_chunk_start);
     }
 };
 

@@ -48,7 +48,8 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
         TE = std::min(TE, te_request);
     TE = std::max(1, std::min(TE, NE));
     // A plane holds the window rows plus the reach of the columns past the
-    // tile's last position: kPwg + (shift spread of the chunk) NN words.
+    // tile's last position: kPwg + (shift spread of the chunk) NN words; a
+    // chunk's A fragments fill at most kMaxG groups.
     *out = taps;
     out->nchunk = 0;
     groups->n = 0;
@@ -56,7 +57,7 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     long win_max = 0;
     while (t < taps.n) {
         int u = t + 1;
-        while (u < taps.n &&
+        while (u < taps.n && u - t < mfmak::kMaxG * mfmak::kGS &&
                mfmak::kPwg + (long)(taps.s[t] - taps.s[u]) * NN <= mfmak::kPlaneWords)
             ++u;
         groups->gb[out->nchunk] = groups->n;
@@ -73,7 +74,7 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     g.n_etiles = (NE + TE - 1) / TE;
     g.lds_win = (int)win_max;
     g.lds_scr = kN3D * TE * NN;
-    g.lds_bytes = 2 * mfmak::kPlaneBytes + (size_t)kN3D * NN * sizeof(double);
+    g.lds_bytes = 0;  // static LDS: two window buffers (the sandwich scratch aliases one)
     return g;
 }
 
@@ -82,10 +83,15 @@ size_t mfma_afrag_bytes(int, int NA, int NB, int Nqz, const GroupTable &g)
     return (size_t)NA * NB * Nqz * g.n * 64 * 32;
 }
 
+size_t mfma_split_offset(int prec, int NA, int NB, int Nqz, const GroupTable &g)
+{
+    return (mfmak::kZeroPage + mfma_afrag_bytes(prec, NA, NB, Nqz, g) + 255) & ~(size_t)255;
+}
+
 size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int Norb,
                       const GroupTable &g)
 {
-    size_t b = (mfma_afrag_bytes(prec, NA, NB, Nqz, g) + 255) & ~(size_t)255;
+    size_t b = mfma_split_offset(prec, NA, NB, Nqz, g);
     if (prec == SSE_BF16X3)
         b += (size_t)Nkz * NE * NA * Norb * Norb * 8;
     return b;

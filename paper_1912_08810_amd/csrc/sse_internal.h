@@ -39,16 +39,23 @@ constexpr int kPmax = kBlock * kR;
 constexpr size_t kLdsBudget = 78 * 1024;
 }  // namespace fp64k
 
-// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.  The G
-// window sits in LDS as two planes of 32-bit words at fixed offsets (bf16 hi
-// and lo pairs, or fp32 re and im), followed by the dH rows.
+// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.  A window
+// (one (b, q, tap chunk)) sits in one of two LDS buffers: two planes of 32-bit
+// words (bf16 hi and lo words, or complex64 re/im interleaved across both),
+// then the chunk's A fragments (at most kMaxG groups of 64 lanes x 32 bytes).
+// The MFMA workspace starts with a zero page (the copy source of rows outside
+// the energy grid), then the A fragments.
 namespace mfmak {
 constexpr int kBlock = 256;
 constexpr int kNT = 4;
 constexpr int kPwg = (kBlock / 64) * kNT * 32;
 constexpr int kGS = 8;
-constexpr int kPlaneWords = 8192;
+constexpr int kPlaneWords = 3584;
 constexpr size_t kPlaneBytes = (size_t)kPlaneWords * 4;
+constexpr int kMaxG = 4;
+constexpr size_t kAfragGroupBytes = 64 * 32;
+constexpr size_t kBufBytes = 2 * kPlaneBytes + kMaxG * kAfragGroupBytes;
+constexpr size_t kZeroPage = 256;
 }  // namespace mfmak
 constexpr int kMaxNorb = 30;
 constexpr int kMaxNB = 50;
@@ -159,8 +166,8 @@ struct GroupTable {
 struct MfmaParams {
     const int32_t *neigh;
     const double *dH;
-    const void *G;      // 8-byte elements: complex64 (fp32) or pre-split bf16 pairs (bf16x3)
-    const void *afrag;  // per (a, b, q, group, lane) A-operand fragments (prep kernel)
+    const void *G;      // complex64 (fp32), or the planar bf16 split: hi words, then lo words
+    const void *afrag;  // workspace: zero page, then the per (a, b, q, group, lane) A fragments
     float2 *Sigma;
     int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
     int32_t TE, n_etiles;
@@ -175,6 +182,7 @@ struct MfmaParams {
 struct MfmaPrepParams {
     const float2 *D;
     void *afrag;
+    void *zero;         // zero page written by the prep kernel
     int32_t NA, NB, Nqz, Nw;
     TapTable taps;
     GroupTable groups;
@@ -216,11 +224,13 @@ hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, siz
 TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
                        TapTable *taps_out, GroupTable *groups_out);
 size_t mfma_afrag_bytes(int prec, int NA, int NB, int Nqz, const GroupTable &g);
-// Workspace of one MFMA instance: A fragments, then (bf16x3) the split copy of G.
+// Workspace of one MFMA instance: zero page, A fragments, then (bf16x3) the
+// planar split copy of G at mfma_split_offset.
+size_t mfma_split_offset(int prec, int NA, int NB, int Nqz, const GroupTable &g);
 size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int Norb,
                       const GroupTable &g);
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s);
-// bf16x3: n complex64 values of G -> n (hi, lo) bf16 pairs of 8 bytes each
+// bf16x3: n complex64 values of G -> n hi words, then n lo words
 hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t s);
 hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStream_t s);
 hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,

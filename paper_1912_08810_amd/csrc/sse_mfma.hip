@@ -37,6 +37,9 @@ constexpr int kNT = mfmak::kNT;               // 32-column tiles per wave
 constexpr int kPwg = mfmak::kPwg;             // output positions per workgroup
 constexpr int kGS = mfmak::kGS;               // taps per group
 constexpr size_t kPlaneBytes = mfmak::kPlaneBytes;
+constexpr size_t kBufBytes = mfmak::kBufBytes;
+constexpr size_t kZeroPage = mfmak::kZeroPage;
+constexpr size_t kAfragGroupBytes = mfmak::kAfragGroupBytes;
 constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -86,6 +89,8 @@ template <int PREC>
 __global__ void k_prep_afrag(const MfmaPrepParams p)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < (int64_t)(kZeroPage / 16))
+        reinterpret_cast<uint4 *>(p.zero)[idx] = make_uint4(0u, 0u, 0u, 0u);
     const int lane = (int)(idx & 63);
     int64_t rest = idx >> 6;
     const int g = (int)(rest % p.groups.n);
@@ -122,59 +127,84 @@ __global__ void k_prep_afrag(const MfmaPrepParams p)
     }
 }
 
-// Copy window rows [0, nrow) (row r = energy ebase + r of the neighbour's G
-// rows, zero outside [0, NE)) into the two LDS planes: word 0 of each 8-byte
-// element to plane 0, word 1 to plane 1.  Wave wv copies rows wv, wv + 4, ...;
-// a row's address is wave-uniform, so only the column offset is per lane.
-template <typename V>
-__device__ __forceinline__ void stage_rows(const uint2 *Gk, size_t strideE, int NE, int ebase,
-                                           int nrow, int NN, int wv, int lane, uint32_t *P0,
-                                           uint32_t *P1)
+typedef __attribute__((address_space(3))) void lds_void;
+
+// One lane's global -> LDS copy of U words (U = 4 or 1) to the wave's base d.
+template <int U>
+__device__ __forceinline__ void lds_copy(const void *src, uint32_t *d)
 {
-    constexpr int kE = sizeof(V) / sizeof(uint2);  // elements per lane load
-    constexpr int kRB = 4;                         // rows in flight per wave
-    const int nv = NN / kE;
-    for (int r0 = wv; r0 < nrow; r0 += 4 * kRB) {
-        for (int c = lane; c < nv; c += 64) {
-            V v[kRB];
-#pragma unroll
-            for (int rb = 0; rb < kRB; ++rb) {
-                const int r = r0 + 4 * rb;
-                const int e = ebase + r;
-                v[rb] = V{};
-                if (r < nrow && e >= 0 && e < NE)
-                    v[rb] = reinterpret_cast<const V *>(Gk + (size_t)e * strideE)[c];
-            }
-#pragma unroll
-            for (int rb = 0; rb < kRB; ++rb) {
-                const int r = r0 + 4 * rb;
-                if (r >= nrow)
-                    break;
-                if constexpr (kE == 2) {
-                    *reinterpret_cast<uint2 *>(P0 + r * NN + 2 * c) = make_uint2(v[rb].x, v[rb].z);
-                    *reinterpret_cast<uint2 *>(P1 + r * NN + 2 * c) = make_uint2(v[rb].y, v[rb].w);
-                } else {
-                    P0[r * NN + c] = v[rb].x;
-                    P1[r * NN + c] = v[rb].y;
-                }
-            }
+    if constexpr (U == 4)
+        __builtin_amdgcn_global_load_lds(src, (lds_void *)d, 16, 0, 0);
+    else
+        __builtin_amdgcn_global_load_lds(src, (lds_void *)d, 4, 0, 0);
+}
+
+// Asynchronous copy global -> LDS of n units of U 32-bit words (U = 4 or 1):
+// unit u goes to dst + u U words and comes from src_of(u) (the caller's map).
+// The copy engine writes each wave's 64 units contiguously, so the LDS base of
+// a wave's instruction is wave-uniform.  Completion is awaited with the
+// vector-memory counter (the barrier that follows waits for it).
+template <int U, typename SrcOf>
+__device__ __forceinline__ void copy_to_lds(uint32_t *dst, int n, SrcOf src_of)
+{
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int base = 0; base < n; base += kBlock) {
+        const int u = base + tid;
+        uint32_t *d = dst + (size_t)(base + wv * 64) * U;
+        if (u < n)
+            lds_copy<U>(src_of(u), d);
+    }
+}
+
+// Copy a window of nrow rows of rowW words into LDS at dst: row r is energy
+// ebase + r of a G row sequence starting at g0 with stride strideW words per
+// energy; rows outside [0, NE) come from the zero page.  Units of U words
+// (rowW % U == 0) are walked incrementally (no division per unit).
+template <int U>
+__device__ __forceinline__ void copy_window(uint32_t *dst, const uint32_t *g0, int64_t strideW,
+                                            int ebase, int NE, int nrow, int rowW,
+                                            const uint32_t *zero)
+{
+    const int upr = rowW / U;
+    const int n = nrow * upr;
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int dr = kBlock / upr, dc = kBlock - (kBlock / upr) * upr;
+    int r = tid / upr, c = tid - (tid / upr) * upr;
+    for (int base = 0; base < n; base += kBlock) {
+        uint32_t *d = dst + (size_t)(base + wv * 64) * U;
+        if (base + tid < n) {
+            const int e = ebase + r;
+            const uint32_t *src = (e >= 0 && e < NE) ? g0 + (int64_t)e * strideW + c * U : zero;
+            lds_copy<U>(src, d);
+        }
+        r += dr;
+        c += dc;
+        if (c >= upr) {
+            c -= upr;
+            ++r;
         }
     }
 }
 
 // One output tile (energies [et TE, et TE + TE) of (k, a)); pp supplies sizes and
 // tap/group tables (a kernel argument or a batch table in global memory), ptr
-// the tensors (aux = A fragments).
+// the tensors (aux = zero page, then A fragments).
+//
+// The tile walks its windows (neighbour b, momentum transfer q, tap chunk c)
+// through two LDS buffers: while the MFMAs consume window n from one buffer,
+// the copy engine fills the other with window n + 1 (G rows and A fragments),
+// so one barrier per window separates them.  After the last window of a
+// neighbour the buffer just consumed holds the binary64 sandwich scratch.
+// bufA and bufB are distinct __shared__ arrays and the window loop alternates
+// them by name, so the compiler can see that reads of one buffer do not
+// depend on the copies in flight into the other.
 template <int PREC>
 __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const TensorPtrs &ptr, int a,
-                                          int k, int et, unsigned char *smem)
+                                          int k, int et, unsigned char *bufA, unsigned char *bufB)
 {
     const auto &p = *pp;
-    uint32_t *P0 = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *P1 = reinterpret_cast<uint32_t *>(smem + kPlaneBytes);
-    double2 *scr = reinterpret_cast<double2 *>(smem);   // sandwich scratch (aliases plane 0)
-    double *ldsA = reinterpret_cast<double *>(smem + 2 * kPlaneBytes);
-
     const int e0 = et * p.TE;
     const int te = min(p.TE, p.NE - e0);
     const int NN = p.NN, No = p.Norb;
@@ -182,10 +212,9 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
     const int Pst = p.TE * NN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
 
     // MFMA column of this lane in tile t: pos0 + 32 t.  Columns at or past P
-    // read in-plane words (the plane holds kPwg + spread NN words) and their
+    // read in-plane words (a plane holds kPwg + spread NN words) and their
     // results are never used: an MFMA column depends on its B column only.
     const int pos0 = wave * kNT * 32 + (lane & 31);
     bool pval[kNT];
@@ -213,193 +242,238 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
         si[r] = 0.0;
     }
 
-    const size_t strideE = (size_t)p.NA * NN;
-    const uint4 *afrag = reinterpret_cast<const uint4 *>(ptr.aux);
+    const int64_t strideE = (int64_t)p.NA * NN;                 // elements per energy row
+    const int64_t g_elems = (int64_t)p.Nkz * p.NE * strideE;
+    const uint32_t *zero = reinterpret_cast<const uint32_t *>(ptr.aux);
+    const unsigned char *afrag = reinterpret_cast<const unsigned char *>(ptr.aux) + kZeroPage;
+    const int nch = p.taps.nchunk;
+    const int nwin = p.NB * p.Nqz * nch;
 
-    for (int b = 0; b < p.NB; ++b) {
-        const int f = ro(ptr.neigh)[(size_t)a * p.NB + b];
-        if ((unsigned)f >= (unsigned)p.NA)
-            continue;
-        double acc[kNT][10];
+    // window w = (b, q, c), c fastest; windows of invalid neighbours are skipped
+    auto neighbour = [&](int b) { return ro(ptr.neigh)[(size_t)a * p.NB + b]; };
+    auto next_valid = [&](int w) {
+        while (w < nwin) {
+            const int f = neighbour(w / (p.Nqz * nch));
+            if ((unsigned)f < (unsigned)p.NA)
+                break;
+            w = (w / (p.Nqz * nch) + 1) * (p.Nqz * nch);
+        }
+        return w;
+    };
+    // start the copies of window w into buffer buf
+    auto issue = [&](int w, unsigned char *buf) {
+        const int b = w / (p.Nqz * nch), q = (w / nch) % p.Nqz, c = w % nch;
+        const int f = neighbour(b);
+        int kk = k - q;
+        if (kk < 0)
+            kk += p.Nkz;
+        const int smax = p.taps.s[p.taps.cb[c]], smin = p.taps.s[p.taps.cb[c + 1] - 1];
+        const int nrow = te + smax - smin;
+        uint32_t *P0 = reinterpret_cast<uint32_t *>(buf);
+        const int64_t row0 = (int64_t)kk * p.NE * strideE + (int64_t)f * NN;  // element index
+        if constexpr (PREC == SSE_BF16X3) {
+            // planar split G: hi words [g_elems], then lo words [g_elems]
+            const uint32_t *Ghi = reinterpret_cast<const uint32_t *>(ptr.G) + row0;
+            uint32_t *P1 = reinterpret_cast<uint32_t *>(buf + kPlaneBytes);
+            if ((NN & 3) == 0) {
+                copy_window<4>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<4>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
+            } else {
+                copy_window<1>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<1>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
+            }
+        } else {
+            // complex64 G, (re, im) interleaved across both planes' space
+            const uint32_t *Gw = reinterpret_cast<const uint32_t *>(ptr.G) + 2 * row0;
+            if ((NN & 1) == 0)
+                copy_window<4>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
+            else
+                copy_window<1>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
+        }
+        const int g0 = p.groups.gb[c], g1 = p.groups.gb[c + 1];
+        const unsigned char *asrc =
+            afrag + ((((size_t)a * p.NB + b) * p.Nqz + q) * p.groups.n + g0) * kAfragGroupBytes;
+        copy_to_lds<4>(reinterpret_cast<uint32_t *>(buf + 2 * kPlaneBytes),
+                       (g1 - g0) * (kAfragGroupBytes / 16),
+                       [&](int u) { return reinterpret_cast<const void *>(asrc + (size_t)u * 16); });
+    };
+
+    double acc[kNT][10];
+    // window w from buf (its copies were issued earlier) while window wn is
+    // copied into other; returns wn
+    auto run_window = [&](int w, unsigned char *buf, unsigned char *other) {
+        const int b = w / (p.Nqz * nch), q = (w / nch) % p.Nqz, c = w % nch;
+        const int wn = next_valid(w + 1);
+        // window w has landed and every wave is done with the other buffer
+        __syncthreads();
+        if (wn < nwin)
+            issue(wn, other);
+        if (q == 0 && c == 0) {
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int v = 0; v < 10; ++v)
+                    acc[t][v] = 0.0;
+        }
+
+        const int t1c = p.taps.cb[c + 1];
+        const int smax = p.taps.s[p.taps.cb[c]];
+        const uint32_t *P0 = reinterpret_cast<const uint32_t *>(buf);
+        const uint32_t *P1 = reinterpret_cast<const uint32_t *>(buf + kPlaneBytes);
+        const uint4 *Ab = reinterpret_cast<const uint4 *>(buf + 2 * kPlaneBytes);
+        f32x16 C[kNT];
+        // one group of kGS taps; the first group of a window starts from a zero
+        // accumulator
+        auto step = [&](int g, int gi, auto first) {
+            constexpr bool kFirst = decltype(first)::value;
+            const uint4 A0 = Ab[gi * 128 + lane * 2];
+            const uint4 A1 = Ab[gi * 128 + lane * 2 + 1];
+            const int tg = p.groups.t0[g];
+            if constexpr (PREC == SSE_BF16X3) {
+                // lanes of half h carry taps tg + 4 h + u, u = 0..3
+                int idx[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ta = tg + u, tb = tg + 4 + u;
+                    const int oa = ta < t1c ? (smax - p.taps.s[ta]) * NN : 0;
+                    const int ob = tb < t1c ? (smax - p.taps.s[tb]) * NN : 0;
+                    idx[u] = pos0 + (h ? ob : oa);
+                }
+                const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
+                const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) {
+                    const uint4 wh = make_uint4(P0[idx[0] + 32 * t], P0[idx[1] + 32 * t],
+                                                P0[idx[2] + 32 * t], P0[idx[3] + 32 * t]);
+                    const uint4 wl = make_uint4(P1[idx[0] + 32 * t], P1[idx[1] + 32 * t],
+                                                P1[idx[2] + 32 * t], P1[idx[3] + 32 * t]);
+                    const bf16x8 bhi = __builtin_bit_cast(bf16x8, wh);
+                    const bf16x8 blo = __builtin_bit_cast(bf16x8, wl);
+                    if constexpr (kFirst)
+                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, f32x16{}, 0, 0, 0);
+                    else
+                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0, 0);
+                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, C[t], 0, 0, 0);
+                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, C[t], 0, 0, 0);
+                }
+            } else {
+                // K = 2 per instruction: lanes of half h carry component h of tap
+                // tg + u, word 2 (position + offset) + h of the interleaved window
+                const float av[8] = {__uint_as_float(A0.x), __uint_as_float(A0.y),
+                                     __uint_as_float(A0.z), __uint_as_float(A0.w),
+                                     __uint_as_float(A1.x), __uint_as_float(A1.y),
+                                     __uint_as_float(A1.z), __uint_as_float(A1.w)};
+                const float *W = reinterpret_cast<const float *>(P0) + h;
+#pragma unroll
+                for (int u = 0; u < kGS; ++u) {
+                    const int t = tg + u;
+                    const int idx = 2 * (pos0 + (t < t1c ? (smax - p.taps.s[t]) * NN : 0));
+#pragma unroll
+                    for (int tt = 0; tt < kNT; ++tt) {
+                        const float bv = W[idx + 64 * tt];
+                        if (kFirst && u == 0)
+                            C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, f32x16{}, 0, 0,
+                                                                         0);
+                        else
+                            C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, C[tt], 0, 0, 0);
+                    }
+                }
+            }
+        };
+        const int g0 = p.groups.gb[c], g1 = p.groups.gb[c + 1];
+        step(g0, 0, std::true_type{});
+        for (int g = g0 + 1; g < g1; ++g)
+            step(g, g - g0, std::false_type{});
+        // fold this window's fp32 partial sums into the binary64 accumulators
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
             for (int v = 0; v < 10; ++v)
-                acc[t][v] = 0.0;
+                acc[t][v] += (double)C[t][v];
 
-        for (int q = 0; q < p.Nqz; ++q) {
-            int kk = k - q;
-            if (kk < 0)
-                kk += p.Nkz;
-            // G rows as 8-byte window elements: float2 (fp32) or the pre-split
-            // bf16 (hi, lo) pairs written by k_split_g (bf16x3)
-            const uint2 *Gk = (const uint2 *)ptr.G + (size_t)kk * p.NE * strideE + (size_t)f * NN;
-            const uint4 *aq = afrag + ((((size_t)a * p.NB + b) * p.Nqz + q) * p.groups.n) * 128;
-            for (int c = 0; c < p.taps.nchunk; ++c) {
-                const int t1c = p.taps.cb[c + 1];
-                const int smax = p.taps.s[p.taps.cb[c]], smin = p.taps.s[t1c - 1];
-                __syncthreads();
-                if ((NN & 1) == 0)
-                    stage_rows<uint4>(Gk, strideE, p.NE, e0 - smax, te + smax - smin, NN, wv,
-                                      lane, P0, P1);
-                else
-                    stage_rows<uint2>(Gk, strideE, p.NE, e0 - smax, te + smax - smin, NN, wv,
-                                      lane, P0, P1);
-                __syncthreads();
-
-                f32x16 C[kNT];
-                // one group of kGS taps; the first group of a window starts
-                // from a zero accumulator
-                auto step = [&](int g, const uint4 &A0, const uint4 &A1, auto first) {
-                    constexpr bool kFirst = decltype(first)::value;
-                    const int tg = p.groups.t0[g];
-                    if constexpr (PREC == SSE_BF16X3) {
-                        // lanes of half h carry taps tg + 4 h + u, u = 0..3
-                        int idx[4];
+        if (q == p.Nqz - 1 && c == nch - 1) {
+            // ---- binary64 sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T,
+            // scratch in the buffer just consumed
+            double2 *scr = reinterpret_cast<double2 *>(buf);
+            double *ldsA = reinterpret_cast<double *>(buf + (size_t)kN3D * Pst * sizeof(double2));
+            __syncthreads();  // window reads are done
+            const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
+            for (int idx = tid; idx < kN3D * NN; idx += kBlock)
+                ldsA[idx] = Ag[idx];
+            double tr[kSR][kN3D], ti[kSR][kN3D];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int ta = tg + u, tb = tg + 4 + u;
-                            const int oa = ta < t1c ? (smax - p.taps.s[ta]) * NN : 0;
-                            const int ob = tb < t1c ? (smax - p.taps.s[tb]) * NN : 0;
-                            idx[u] = pos0 + (h ? ob : oa);
-                        }
-                        const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
-                        const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
+            for (int r = 0; r < kSR; ++r)
 #pragma unroll
-                        for (int t = 0; t < kNT; ++t) {
-                            const uint4 wh = make_uint4(P0[idx[0] + 32 * t], P0[idx[1] + 32 * t],
-                                                        P0[idx[2] + 32 * t], P0[idx[3] + 32 * t]);
-                            const uint4 wl = make_uint4(P1[idx[0] + 32 * t], P1[idx[1] + 32 * t],
-                                                        P1[idx[2] + 32 * t], P1[idx[3] + 32 * t]);
-                            const bf16x8 bhi = __builtin_bit_cast(bf16x8, wh);
-                            const bf16x8 blo = __builtin_bit_cast(bf16x8, wl);
-                            if constexpr (kFirst)
-                                C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, f32x16{}, 0,
-                                                                               0, 0);
-                            else
-                                C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0,
-                                                                               0);
-                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, C[t], 0, 0, 0);
-                            C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, C[t], 0, 0, 0);
-                        }
-                    } else {
-                        // K = 2 per instruction: lanes of half h carry component h
-                        // (plane h) of tap tg + u
-                        const float av[8] = {__uint_as_float(A0.x), __uint_as_float(A0.y),
-                                             __uint_as_float(A0.z), __uint_as_float(A0.w),
-                                             __uint_as_float(A1.x), __uint_as_float(A1.y),
-                                             __uint_as_float(A1.z), __uint_as_float(A1.w)};
-                        const float *Ph = reinterpret_cast<const float *>(h ? P1 : P0);
-#pragma unroll
-                        for (int u = 0; u < kGS; ++u) {
-                            const int t = tg + u;
-                            const int idx = pos0 + (t < t1c ? (smax - p.taps.s[t]) * NN : 0);
-#pragma unroll
-                            for (int tt = 0; tt < kNT; ++tt) {
-                                const float bv = Ph[idx + 32 * tt];
-                                if (kFirst && u == 0)
-                                    C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, f32x16{},
-                                                                                 0, 0, 0);
-                                else
-                                    C[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, C[tt], 0,
-                                                                                 0, 0);
-                            }
-                        }
-                    }
-                };
-                const int g0 = p.groups.gb[c], g1 = p.groups.gb[c + 1];
-                uint4 A0 = aq[(size_t)g0 * 128 + lane * 2];
-                uint4 A1 = aq[(size_t)g0 * 128 + lane * 2 + 1];
-                uint4 N0 = A0, N1 = A1;
-                if (g0 + 1 < g1) {
-                    N0 = aq[(size_t)(g0 + 1) * 128 + lane * 2];
-                    N1 = aq[(size_t)(g0 + 1) * 128 + lane * 2 + 1];
+                for (int j = 0; j < kN3D; ++j) {
+                    tr[r][j] = 0.0;
+                    ti[r][j] = 0.0;
                 }
-                step(g0, A0, A1, std::true_type{});
-                for (int g = g0 + 1; g < g1; ++g) {
-                    A0 = N0;
-                    A1 = N1;
-                    if (g + 1 < g1) {
-                        N0 = aq[(size_t)(g + 1) * 128 + lane * 2];
-                        N1 = aq[(size_t)(g + 1) * 128 + lane * 2 + 1];
-                    }
-                    step(g, A0, A1, std::false_type{});
-                }
-                // fold this window's fp32 partial sums into the binary64 accumulators
+#pragma unroll
+            for (int i = 0; i < kN3D; ++i) {
+                if (i > 0)
+                    __syncthreads();
+                // C rows held by this lane: row = 8 (v / 4) + 4 h + v % 4, row = 2 ij + re/im
 #pragma unroll
                 for (int t = 0; t < kNT; ++t)
 #pragma unroll
-                    for (int v = 0; v < 10; ++v)
-                        acc[t][v] += (double)C[t][v];
-            }
-        }
-
-        // ---- binary64 sandwich: Sigma += sum_ij dH_i Gh_ij dH_j^T
-        __syncthreads();
-        const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
-        for (int idx = tid; idx < kN3D * NN; idx += kBlock)
-            ldsA[idx] = Ag[idx];
-        double tr[kSR][kN3D], ti[kSR][kN3D];
-#pragma unroll
-        for (int r = 0; r < kSR; ++r)
-#pragma unroll
-            for (int j = 0; j < kN3D; ++j) {
-                tr[r][j] = 0.0;
-                ti[r][j] = 0.0;
-            }
-#pragma unroll
-        for (int i = 0; i < kN3D; ++i) {
-            if (i > 0)
+                    for (int v = 0; v < 10; v += 2) {
+                        const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+                        const int ij = row >> 1;
+                        if (ij < kNF && ij / kN3D == i && pval[t])
+                            scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
+                                make_double2(acc[t][v], acc[t][v + 1]);
+                    }
                 __syncthreads();
-            // C rows held by this lane: row = 8 (v / 4) + 4 h + v % 4, row = 2 ij + re/im
 #pragma unroll
-            for (int t = 0; t < kNT; ++t)
+                for (int r = 0; r < kSR; ++r) {
+                    const int base = pe[r] * NN + pn[r];
+                    const double *Arow = ldsA + i * NN + pm[r] * No;
+                    for (int l = 0; l < No; ++l) {
+                        const double am = Arow[l];
 #pragma unroll
-                for (int v = 0; v < 10; v += 2) {
-                    const int row = 8 * (v >> 2) + 4 * h + (v & 3);
-                    const int ij = row >> 1;
-                    if (ij < kNF && ij / kN3D == i && pval[t])
-                        scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
-                            make_double2(acc[t][v], acc[t][v + 1]);
+                        for (int j = 0; j < kN3D; ++j) {
+                            const double2 sv = scr[j * Pst + base + l * No];
+                            tr[r][j] = fma(am, sv.x, tr[r][j]);
+                            ti[r][j] = fma(am, sv.y, ti[r][j]);
+                        }
+                    }
                 }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kSR; ++r)
+                if (sval[r])
+#pragma unroll
+                    for (int j = 0; j < kN3D; ++j)
+                        scr[j * Pst + spos[r]] = make_double2(tr[r][j], ti[r][j]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kSR; ++r) {
-                const int base = pe[r] * NN + pn[r];
-                const double *Arow = ldsA + i * NN + pm[r] * No;
-                for (int l = 0; l < No; ++l) {
-                    const double am = Arow[l];
+                const int base = pe[r] * NN + pm[r] * No;
 #pragma unroll
-                    for (int j = 0; j < kN3D; ++j) {
-                        const double2 s = scr[j * Pst + base + l * No];
-                        tr[r][j] = fma(am, s.x, tr[r][j]);
-                        ti[r][j] = fma(am, s.y, ti[r][j]);
+                for (int j = 0; j < kN3D; ++j) {
+                    const double *Arow = ldsA + j * NN + pn[r] * No;
+                    for (int l = 0; l < No; ++l) {
+                        const double2 sv = scr[j * Pst + base + l];
+                        const double am = Arow[l];
+                        sr[r] = fma(sv.x, am, sr[r]);
+                        si[r] = fma(sv.y, am, si[r]);
                     }
                 }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kSR; ++r)
-            if (sval[r])
-#pragma unroll
-                for (int j = 0; j < kN3D; ++j)
-                    scr[j * Pst + spos[r]] = make_double2(tr[r][j], ti[r][j]);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kSR; ++r) {
-            const int base = pe[r] * NN + pm[r] * No;
-#pragma unroll
-            for (int j = 0; j < kN3D; ++j) {
-                const double *Arow = ldsA + j * NN + pn[r] * No;
-                for (int l = 0; l < No; ++l) {
-                    const double2 s = scr[j * Pst + base + l];
-                    const double am = Arow[l];
-                    sr[r] = fma(s.x, am, sr[r]);
-                    si[r] = fma(s.y, am, si[r]);
-                }
-            }
-        }
+        return wn;
+    };
+    int w = next_valid(0);
+    if (w < nwin)
+        issue(w, bufA);
+    // every issue is followed by a window that begins with a barrier, so no
+    // copy is in flight when the loop ends
+    while (w < nwin) {
+        w = run_window(w, bufA, bufB);
+        if (w >= nwin)
+            break;
+        w = run_window(w, bufB, bufA);
     }
 
     float2 *Sk = (float2 *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
@@ -414,8 +488,9 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
     }
 }
 
-// bf16x3: every complex64 value of G as (re_hi | im_hi << 16, re_lo | im_lo << 16).
-__global__ void k_split_g(const float2 *__restrict__ G, uint2 *__restrict__ out, int64_t n)
+// bf16x3: every complex64 value of G as a hi word (re_hi | im_hi << 16) in
+// out[0, n) and a lo word (re_lo | im_lo << 16) in out[n, 2 n).
+__global__ void k_split_g(const float2 *__restrict__ G, uint32_t *__restrict__ out, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -423,28 +498,32 @@ __global__ void k_split_g(const float2 *__restrict__ G, uint2 *__restrict__ out,
         uint32_t rh, rl, ih, il;
         split_bf16(v.x, rh, rl);
         split_bf16(v.y, ih, il);
-        out[i] = make_uint2(rh | ih << 16, rl | il << 16);
+        out[i] = rh | ih << 16;
+        out[n + i] = rl | il << 16;
     }
 }
 
 template <int PREC>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) unsigned char bufA[kBufBytes];
+    __shared__ __align__(16) unsigned char bufB[kBufBytes];
     int64_t L = xcd_remap(blockIdx.x, p.n_wg);
     const int k = (int)(L % p.Nkz);
     L /= p.Nkz;
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
-    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};  // G: 8-byte elements
-    mfma_tile<PREC>(ro(&p), ptr, a, k, et, smem);
+    // G: planar bf16 split (bf16x3) or complex64 (fp32); aux: zero page, A fragments
+    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
+    mfma_tile<PREC>(ro(&p), ptr, a, k, et, bufA, bufB);
 }
 
 // Persistent form over a batch's work queues (see batch_pull).
 template <int PREC>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLaunch bl)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) unsigned char bufA[kBufBytes];
+    __shared__ __align__(16) unsigned char bufB[kBufBytes];
     __shared__ int s_tile[4];
     const int home = blockIdx.x & 7;
     for (;;) {
@@ -459,7 +538,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLa
         if (inst < 0)
             break;
         mfma_tile<PREC>(ro(reinterpret_cast<const MfmaParams *>(bl.params)) + inst, bl.ptr[inst],
-                        a, k, et, smem);
+                        a, k, et, bufA, bufB);
     }
 }
 
@@ -473,7 +552,7 @@ hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t 
     if (g < 1)
         g = 1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_split_g, dim3((unsigned)g), dim3(256), 0, s, G, (uint2 *)out, n);
+    hipLaunchKernelGGL(k_split_g, dim3((unsigned)g), dim3(256), 0, s, G, (uint32_t *)out, n);
     return hipGetLastError();
 }
 
@@ -493,20 +572,11 @@ hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
+// The MFMA kernels use static LDS only (two window buffers); lds_bytes is the
+// dynamic amount, zero for these kernels.
 hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,
                                   hipStream_t s)
 {
-    static bool attr_set[2] = {false, false};
-    const void *fn = prec == SSE_BF16X3 ? (const void *)k_sse_mfma_persistent<SSE_BF16X3>
-                                        : (const void *)k_sse_mfma_persistent<SSE_FP32>;
-    const int which = prec == SSE_BF16X3;
-    if (!attr_set[which]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(2 * kPlaneBytes + 16 * 1024));
-        if (e != hipSuccess)
-            return e;
-        attr_set[which] = true;
-    }
     if (prec == SSE_BF16X3) {
         (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma_persistent<SSE_BF16X3>, dim3(grid), dim3(kBlock), lds_bytes,
@@ -525,17 +595,6 @@ hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStrea
         return hipSuccess;
     if (p.n_wg > 0x7fffffffLL)
         return hipErrorInvalidConfiguration;
-    static bool attr_set[2] = {false, false};
-    const void *fn = prec == SSE_BF16X3 ? (const void *)k_sse_mfma<SSE_BF16X3>
-                                        : (const void *)k_sse_mfma<SSE_FP32>;
-    const int which = prec == SSE_BF16X3;
-    if (!attr_set[which]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(2 * kPlaneBytes + 16 * 1024));
-        if (e != hipSuccess)
-            return e;
-        attr_set[which] = true;
-    }
     if (prec == SSE_BF16X3) {
         (void)hipGetLastError();
         hipLaunchKernelGGL(k_sse_mfma<SSE_BF16X3>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes,

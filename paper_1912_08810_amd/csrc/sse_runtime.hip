@@ -225,7 +225,8 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
         } else {
             MfmaPrepParams pp{};
             pp.D = (const float2 *)D;
-            pp.afrag = wsfree;
+            pp.zero = wsfree;
+            pp.afrag = (char *)wsfree + mfmak::kZeroPage;
             pp.NA = d.NA;
             pp.NB = d.NB;
             pp.Nqz = d.Nqz;
@@ -237,9 +238,8 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
                 return hip_fail(e, "MFMA prep launch");
             const void *Gm = G;
             if (d.prec == SSE_BF16X3) {
-                char *split = (char *)wsfree +
-                              ((mfma_afrag_bytes(d.prec, d.NA, d.NB, d.Nqz, I.groups) + 255) &
-                               ~(size_t)255);
+                char *split = (char *)wsfree + mfma_split_offset(d.prec, d.NA, d.NB, d.Nqz,
+                                                                 I.groups);
                 e = mfma_split_launch((const float2 *)G, split, (int64_t)g_elems, s);
                 if (e != hipSuccess)
                     return hip_fail(e, "G split launch");
@@ -438,8 +438,7 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
             bl.ptr[t].aux = ws + P->afrag_off[t];
             if (d.prec == SSE_BF16X3) {
                 char *split = ws + P->afrag_off[t] +
-                              ((mfma_afrag_bytes(d.prec, d.NA, d.NB, d.Nqz, P->inst[t].groups) +
-                                255) & ~(size_t)255);
+                              mfma_split_offset(d.prec, d.NA, d.NB, d.Nqz, P->inst[t].groups);
                 e = mfma_split_launch((const float2 *)bl.ptr[t].G, split, (int64_t)g_elems, s);
                 if (e != hipSuccess)
                     return hip_fail(e, "G split launch");
@@ -448,7 +447,8 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
             if (!fp64_arith(d.prec)) {
                 MfmaPrepParams pp{};
                 pp.D = (const float2 *)bl.ptr[t].D;
-                pp.afrag = ws + P->afrag_off[t];
+                pp.zero = ws + P->afrag_off[t];
+                pp.afrag = ws + P->afrag_off[t] + mfmak::kZeroPage;
                 pp.NA = d.NA;
                 pp.NB = d.NB;
                 pp.Nqz = d.Nqz;

@@ -33,7 +33,7 @@ def bucket_of(NE: int, Nw: int):
 
 def candidates(prec: int, Norb: int):
     nn = Norb * Norb
-    tmax = max(1, (1024 if prec in (0, 3) else 512) // nn)
+    tmax = max(1, 1024 // nn)  # output positions per workgroup: 1024 on both paths
     c = sorted({tmax, max(1, tmax * 3 // 4), max(1, tmax // 2), max(1, tmax // 4), 1},
                reverse=True)
     return c

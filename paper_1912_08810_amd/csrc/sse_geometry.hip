@@ -74,7 +74,7 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     g.n_etiles = (NE + TE - 1) / TE;
     g.lds_win = (int)win_max;
     g.lds_scr = kN3D * TE * NN;
-    g.lds_bytes = 0;  // static LDS: two window buffers (the sandwich scratch aliases one)
+    g.lds_bytes = 0;  // static LDS: two window buffers and the sandwich region
     return g;
 }
 

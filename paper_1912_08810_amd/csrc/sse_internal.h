@@ -39,23 +39,26 @@ constexpr int kPmax = kBlock * kR;
 constexpr size_t kLdsBudget = 78 * 1024;
 }  // namespace fp64k
 
-// MFMA kernel: 4 waves x 4 tiles of 32 columns; taps in groups of 8.  A window
-// (one (b, q, tap chunk)) sits in one of two LDS buffers: two planes of 32-bit
-// words (bf16 hi and lo words, or complex64 re/im interleaved across both),
-// then the chunk's A fragments (at most kMaxG groups of 64 lanes x 32 bytes).
-// The MFMA workspace starts with a zero page (the copy source of rows outside
-// the energy grid), then the A fragments.
+// MFMA kernel: 8 waves x 4 tiles of 32 columns (one workgroup per CU, two
+// waves per SIMD); taps in groups of 8.  A window (one (b, q, tap chunk)) sits
+// in one of two LDS buffers: two planes of 32-bit words (bf16 hi and lo words,
+// or complex64 re/im interleaved across both), then the chunk's A fragments (at
+// most kMaxG groups of 64 lanes x 32 bytes).  The binary64 sandwich has its own
+// LDS region.  The MFMA workspace starts with a zero page (the copy source of
+// rows outside the energy grid), then the A fragments.
 namespace mfmak {
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
 constexpr int kNT = 4;
 constexpr int kPwg = (kBlock / 64) * kNT * 32;
 constexpr int kGS = 8;
-constexpr int kPlaneWords = 3584;
+constexpr int kPlaneWords = 4096;
 constexpr size_t kPlaneBytes = (size_t)kPlaneWords * 4;
 constexpr int kMaxG = 4;
 constexpr size_t kAfragGroupBytes = 64 * 32;
 constexpr size_t kBufBytes = 2 * kPlaneBytes + kMaxG * kAfragGroupBytes;
 constexpr size_t kZeroPage = 256;
+// sandwich scratch: three planes of kPwg complex128, then dH rows (Norb <= 22)
+constexpr size_t kSandBytes = 3 * (size_t)kPwg * 16 + 3 * 484 * 8;
 }  // namespace mfmak
 constexpr int kMaxNorb = 30;
 constexpr int kMaxNB = 50;

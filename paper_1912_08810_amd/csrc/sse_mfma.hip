@@ -40,6 +40,7 @@ constexpr size_t kPlaneBytes = mfmak::kPlaneBytes;
 constexpr size_t kBufBytes = mfmak::kBufBytes;
 constexpr size_t kZeroPage = mfmak::kZeroPage;
 constexpr size_t kAfragGroupBytes = mfmak::kAfragGroupBytes;
+constexpr size_t kSandBytes = mfmak::kSandBytes;
 constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -202,7 +203,8 @@ __device__ __forceinline__ void copy_window(uint32_t *dst, const uint32_t *g0, i
 // depend on the copies in flight into the other.
 template <int PREC>
 __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const TensorPtrs &ptr, int a,
-                                          int k, int et, unsigned char *bufA, unsigned char *bufB)
+                                          int k, int et, unsigned char *bufA, unsigned char *bufB,
+                                          unsigned char *sand)
 {
     const auto &p = *pp;
     const int e0 = et * p.TE;
@@ -341,21 +343,32 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                 }
                 const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
                 const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
+                // all four tiles' B operands first, then the three products in
+                // rounds over the tiles: consecutive MFMAs are independent
+                bf16x8 bhi[kNT], blo[kNT];
 #pragma unroll
                 for (int t = 0; t < kNT; ++t) {
-                    const uint4 wh = make_uint4(P0[idx[0] + 32 * t], P0[idx[1] + 32 * t],
-                                                P0[idx[2] + 32 * t], P0[idx[3] + 32 * t]);
-                    const uint4 wl = make_uint4(P1[idx[0] + 32 * t], P1[idx[1] + 32 * t],
-                                                P1[idx[2] + 32 * t], P1[idx[3] + 32 * t]);
-                    const bf16x8 bhi = __builtin_bit_cast(bf16x8, wh);
-                    const bf16x8 blo = __builtin_bit_cast(bf16x8, wl);
-                    if constexpr (kFirst)
-                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, f32x16{}, 0, 0, 0);
-                    else
-                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, C[t], 0, 0, 0);
-                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, C[t], 0, 0, 0);
-                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, C[t], 0, 0, 0);
+                    bhi[t] = __builtin_bit_cast(
+                        bf16x8, make_uint4(P0[idx[0] + 32 * t], P0[idx[1] + 32 * t],
+                                           P0[idx[2] + 32 * t], P0[idx[3] + 32 * t]));
+                    blo[t] = __builtin_bit_cast(
+                        bf16x8, make_uint4(P1[idx[0] + 32 * t], P1[idx[1] + 32 * t],
+                                           P1[idx[2] + 32 * t], P1[idx[3] + 32 * t]));
                 }
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) {
+                    if constexpr (kFirst)
+                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], f32x16{}, 0, 0,
+                                                                       0);
+                    else
+                        C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], C[t], 0, 0, 0);
+                }
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], C[t], 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+                    C[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], C[t], 0, 0, 0);
             } else {
                 // K = 2 per instruction: lanes of half h carry component h of tap
                 // tg + u, word 2 (position + offset) + h of the interleaved window
@@ -392,11 +405,10 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                 acc[t][v] += (double)C[t][v];
 
         if (q == p.Nqz - 1 && c == nch - 1) {
-            // ---- binary64 sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T,
-            // scratch in the buffer just consumed
-            double2 *scr = reinterpret_cast<double2 *>(buf);
-            double *ldsA = reinterpret_cast<double *>(buf + (size_t)kN3D * Pst * sizeof(double2));
-            __syncthreads();  // window reads are done
+            // ---- binary64 sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T
+            double2 *scr = reinterpret_cast<double2 *>(sand);
+            double *ldsA = reinterpret_cast<double *>(sand + (size_t)kN3D * Pst * sizeof(double2));
+            __syncthreads();  // the previous neighbour's sandwich reads are done
             const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
             for (int idx = tid; idx < kN3D * NN; idx += kBlock)
                 ldsA[idx] = Ag[idx];
@@ -504,10 +516,11 @@ __global__ void k_split_g(const float2 *__restrict__ G, uint32_t *__restrict__ o
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
+__global__ __launch_bounds__(kBlock, 1) void k_sse_mfma(const MfmaParams p)
 {
     __shared__ __align__(16) unsigned char bufA[kBufBytes];
     __shared__ __align__(16) unsigned char bufB[kBufBytes];
+    __shared__ __align__(16) unsigned char sand[kSandBytes];
     int64_t L = xcd_remap(blockIdx.x, p.n_wg);
     const int k = (int)(L % p.Nkz);
     L /= p.Nkz;
@@ -515,15 +528,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma(const MfmaParams p)
     const int a = (int)(L / p.n_etiles);
     // G: planar bf16 split (bf16x3) or complex64 (fp32); aux: zero page, A fragments
     const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
-    mfma_tile<PREC>(ro(&p), ptr, a, k, et, bufA, bufB);
+    mfma_tile<PREC>(ro(&p), ptr, a, k, et, bufA, bufB, sand);
 }
 
 // Persistent form over a batch's work queues (see batch_pull).
 template <int PREC>
-__global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLaunch bl)
+__global__ __launch_bounds__(kBlock, 1) void k_sse_mfma_persistent(const BatchLaunch bl)
 {
     __shared__ __align__(16) unsigned char bufA[kBufBytes];
     __shared__ __align__(16) unsigned char bufB[kBufBytes];
+    __shared__ __align__(16) unsigned char sand[kSandBytes];
     __shared__ int s_tile[4];
     const int home = blockIdx.x & 7;
     for (;;) {
@@ -538,7 +552,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_mfma_persistent(const BatchLa
         if (inst < 0)
             break;
         mfma_tile<PREC>(ro(reinterpret_cast<const MfmaParams *>(bl.params)) + inst, bl.ptr[inst],
-                        a, k, et, bufA, bufB);
+                        a, k, et, bufA, bufB, sand);
     }
 }
 

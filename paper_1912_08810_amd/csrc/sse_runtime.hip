@@ -392,7 +392,8 @@ hipError_t build_batch_tables(sse_plan_s *P)
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return e;
-    P->grid = std::max(8, 2 * cus);
+    // two binary64 workgroups per CU (256 threads each), one MFMA workgroup (512)
+    P->grid = std::max(8, (fp64_arith(P->inst[0].d.prec) ? 2 : 1) * cus);
     return hipSuccess;
 }
 

@@ -51,9 +51,9 @@ constexpr int kBlock = 512;
 constexpr int kNT = 4;
 constexpr int kPwg = (kBlock / 64) * kNT * 32;
 constexpr int kGS = 8;
-constexpr int kPlaneWords = 4096;
+constexpr int kPlaneWords = 5120;
 constexpr size_t kPlaneBytes = (size_t)kPlaneWords * 4;
-constexpr int kMaxG = 4;
+constexpr int kMaxG = 5;
 constexpr size_t kAfragGroupBytes = 64 * 32;
 constexpr size_t kBufBytes = 2 * kPlaneBytes + kMaxG * kAfragGroupBytes;
 constexpr size_t kZeroPage = 256;

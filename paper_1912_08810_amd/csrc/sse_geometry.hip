@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "sse_internal.h"
+#include "sse_mfma.h"
 
 namespace sse {
 

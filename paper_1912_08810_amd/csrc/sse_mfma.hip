@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "sse_internal.h"
+#include "sse_mfma.h"
 
 namespace sse {
 

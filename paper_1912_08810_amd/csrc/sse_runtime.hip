@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "sse_internal.h"
+#include "sse_mfma.h"
 
 using namespace sse;
 

@@ -3,6 +3,7 @@
 // sums get known values (|diff|^2 = 1e-12, |ref|^2 = 1), and every launch
 // reports hipGetLastError() as the real launches do.
 #include "sse_internal.h"
+#include "sse_mfma.h"
 namespace sse {
 hipError_t fp64_launch(const Fp64Params &, bool, size_t, hipStream_t) { return hipSuccess; }
 hipError_t fp64_persistent_launch(const BatchLaunch &, bool, int, size_t, hipStream_t) { return hipSuccess; }

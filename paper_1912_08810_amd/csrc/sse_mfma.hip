@@ -28,6 +28,7 @@
 
 #include "sse_internal.h"
 #include "sse_mfma.h"
+#include "sse_copy.h"
 
 namespace sse {
 
@@ -129,67 +130,6 @@ __global__ void k_prep_afrag(const MfmaPrepParams p)
     }
 }
 
-typedef __attribute__((address_space(3))) void lds_void;
-
-// One lane's global -> LDS copy of U words (U = 4 or 1) to the wave's base d.
-template <int U>
-__device__ __forceinline__ void lds_copy(const void *src, uint32_t *d)
-{
-    if constexpr (U == 4)
-        __builtin_amdgcn_global_load_lds(src, (lds_void *)d, 16, 0, 0);
-    else
-        __builtin_amdgcn_global_load_lds(src, (lds_void *)d, 4, 0, 0);
-}
-
-// Asynchronous copy global -> LDS of n units of U 32-bit words (U = 4 or 1):
-// unit u goes to dst + u U words and comes from src_of(u) (the caller's map).
-// The copy engine writes each wave's 64 units contiguously, so the LDS base of
-// a wave's instruction is wave-uniform.  Completion is awaited with the
-// vector-memory counter (the barrier that follows waits for it).
-template <int U, typename SrcOf>
-__device__ __forceinline__ void copy_to_lds(uint32_t *dst, int n, SrcOf src_of)
-{
-    const int tid = threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int base = 0; base < n; base += kBlock) {
-        const int u = base + tid;
-        uint32_t *d = dst + (size_t)(base + wv * 64) * U;
-        if (u < n)
-            lds_copy<U>(src_of(u), d);
-    }
-}
-
-// Copy a window of nrow rows of rowW words into LDS at dst: row r is energy
-// ebase + r of a G row sequence starting at g0 with stride strideW words per
-// energy; rows outside [0, NE) come from the zero page.  Units of U words
-// (rowW % U == 0) are walked incrementally (no division per unit).
-template <int U>
-__device__ __forceinline__ void copy_window(uint32_t *dst, const uint32_t *g0, int64_t strideW,
-                                            int ebase, int NE, int nrow, int rowW,
-                                            const uint32_t *zero)
-{
-    const int upr = rowW / U;
-    const int n = nrow * upr;
-    const int tid = threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int dr = kBlock / upr, dc = kBlock - (kBlock / upr) * upr;
-    int r = tid / upr, c = tid - (tid / upr) * upr;
-    for (int base = 0; base < n; base += kBlock) {
-        uint32_t *d = dst + (size_t)(base + wv * 64) * U;
-        if (base + tid < n) {
-            const int e = ebase + r;
-            const uint32_t *src = (e >= 0 && e < NE) ? g0 + (int64_t)e * strideW + c * U : zero;
-            lds_copy<U>(src, d);
-        }
-        r += dr;
-        c += dc;
-        if (c >= upr) {
-            c -= upr;
-            ++r;
-        }
-    }
-}
-
 // One output tile (energies [et TE, et TE + TE) of (k, a)); pp supplies sizes and
 // tap/group tables (a kernel argument or a batch table in global memory), ptr
 // the tensors (aux = zero page, then A fragments).
@@ -279,24 +219,24 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
             const uint32_t *Ghi = reinterpret_cast<const uint32_t *>(ptr.G) + row0;
             uint32_t *P1 = reinterpret_cast<uint32_t *>(buf + kPlaneBytes);
             if ((NN & 3) == 0) {
-                copy_window<4>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
-                copy_window<4>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<4, kBlock>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<4, kBlock>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
             } else {
-                copy_window<1>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
-                copy_window<1>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<1, kBlock>(P0, Ghi, strideE, e0 - smax, p.NE, nrow, NN, zero);
+                copy_window<1, kBlock>(P1, Ghi + g_elems, strideE, e0 - smax, p.NE, nrow, NN, zero);
             }
         } else {
             // complex64 G, (re, im) interleaved across both planes' space
             const uint32_t *Gw = reinterpret_cast<const uint32_t *>(ptr.G) + 2 * row0;
             if ((NN & 1) == 0)
-                copy_window<4>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
+                copy_window<4, kBlock>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
             else
-                copy_window<1>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
+                copy_window<1, kBlock>(P0, Gw, 2 * strideE, e0 - smax, p.NE, nrow, 2 * NN, zero);
         }
         const int g0 = p.groups.gb[c], g1 = p.groups.gb[c + 1];
         const unsigned char *asrc =
             afrag + ((((size_t)a * p.NB + b) * p.Nqz + q) * p.groups.n + g0) * kAfragGroupBytes;
-        copy_to_lds<4>(reinterpret_cast<uint32_t *>(buf + 2 * kPlaneBytes),
+        copy_to_lds<4, kBlock>(reinterpret_cast<uint32_t *>(buf + 2 * kPlaneBytes),
                        (g1 - g0) * (kAfragGroupBytes / 16),
                        [&](int u) { return reinterpret_cast<const void *>(asrc + (size_t)u * 16); });
     };

@@ -27,6 +27,22 @@ def test_fp64_arithmetic_on_complex64_storage():
         assert e <= 1e-7
 
 
+@pytest.mark.parametrize("Norb,shift", [(5, (0, 9, 18, 27, 36, 43, -9, 3)),
+                                         (10, (0, 12, 24, 36, 43, -12, 5, -43))])
+def test_fp64_arithmetic_on_complex64_storage_wide_spread(Norb, shift):
+    # odd Norb^2 rows of complex64 are copied in 4-byte units; the spreads cut
+    # the taps into several windows
+    prob = configs.Problem(NA=7, NB=3, Norb=Norb, Nkz=2, Nqz=2, NE=44, Nw=len(shift),
+                           shift=shift)
+    dp = gu.DeviceProblem(prob, 43 + Norb, ncomp=1, fp32=True, scaled=True)
+    assert gu.run_sse(dp, prec=3) == 0
+    got = dp.sigma_host(0)
+    want = gu.oracle_full(dp, 0)
+    e = gu.rel_fro(got, want)
+    print(f"  fp64c64 Norb={Norb}: rel_fro={e:.3e}", flush=True)
+    assert e <= 1e-7
+
+
 def setup_check(prec):
     import torch
     sse = _sse()

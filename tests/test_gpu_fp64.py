@@ -51,7 +51,17 @@ def test_ragged_tiles_unsorted_negative_shifts():
     check_full(dp)
 
 
-@pytest.mark.parametrize("Norb", [1, 3, 7, 12, 16, 30])
+def test_wide_shift_spread_many_chunks():
+    # shift spread 78 at Norb=10: the taps are cut into several windows per
+    # (b, q); shifts of +-39 with NE=40 read almost only zero-padded rows
+    prob = configs.Problem(NA=6, NB=3, Norb=10, Nkz=2, Nqz=2, NE=40, Nw=9,
+                           shift=(0, 8, 16, 24, 32, 39, -8, -16, -39))
+    dp = gu.DeviceProblem(prob, 13)
+    assert run(dp) == 0
+    check_full(dp)
+
+
+@pytest.mark.parametrize("Norb", [1, 3, 7, 12, 16, 23, 24, 30])
 def test_orbital_counts(Norb):
     prob = configs.Problem(NA=9, NB=3, Norb=Norb, Nkz=3, Nqz=2, NE=23, Nw=6)
     dp = gu.DeviceProblem(prob, 100 + Norb)

@@ -12,7 +12,7 @@ namespace sse {
 // waves per SIMD); taps in groups of 8.  A window (one (b, q, tap chunk)) sits
 // in one of two LDS buffers: two planes of 32-bit words (bf16 hi and lo words,
 // or complex64 re/im interleaved across both), then the chunk's A fragments (at
-// most kMaxG groups of 64 lanes x 32 bytes).  The binary64 sandwich has its own
+// most kMaxG groups of 64 lanes x 32 bytes).  The fp32 sandwich has its own
 // LDS region.  The MFMA workspace starts with a zero page (the copy source of
 // rows outside the energy grid), then the A fragments.
 namespace mfmak {
@@ -26,8 +26,8 @@ constexpr int kMaxG = 5;
 constexpr size_t kAfragGroupBytes = 64 * 32;
 constexpr size_t kBufBytes = 2 * kPlaneBytes + kMaxG * kAfragGroupBytes;
 constexpr size_t kZeroPage = 256;
-// sandwich scratch: three planes of kPwg complex128, then dH rows (Norb <= 22)
-constexpr size_t kSandBytes = 3 * (size_t)kPwg * 16 + 3 * 484 * 8;
+// sandwich scratch: three planes of kPwg complex64, then dH rows as fp32 (Norb <= 22)
+constexpr size_t kSandBytes = 3 * (size_t)kPwg * 8 + 3 * 484 * 4;
 }  // namespace mfmak
 
 // Groups of eight consecutive taps of one chunk (the K extent of one MFMA

@@ -1,6 +1,6 @@
 // sse_mfma.hip -- complex64-storage scattering self-energy on the gfx950
 // matrix cores: the (qz, w) tap filters of Eq. (3) (Sec. 2) as a GEMM on
-// MFMA, the dH sandwich in binary64.
+// MFMA, the dH sandwich as fp32 block products.
 //
 // For one bond (a, b) with neighbour f, the tap sum
 //   Gh_ij[k, e, c] = sum_{q, w} Dt[q, w, a, b, i, j] G[(k - q) mod Nkz, e - s_w, f, c]
@@ -20,7 +20,8 @@
 //             operand x is split x = hi + lo (bf16 hi, bf16 lo = x - hi) and the
 //             product is hi*hi + hi*lo + lo*hi.
 // Accumulation: fp32 inside the MFMA over the taps of one energy window (one
-// qz row), binary64 across qz rows, neighbours and in the sandwich.
+// qz row), binary64 across windows (the sum over qz and the tap chunks) and
+// over neighbours; the sandwich's Norb x Norb block products are fp32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -346,20 +347,23 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                 acc[t][v] += (double)C[t][v];
 
         if (q == p.Nqz - 1 && c == nch - 1) {
-            // ---- binary64 sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T
-            double2 *scr = reinterpret_cast<double2 *>(sand);
-            double *ldsA = reinterpret_cast<double *>(sand + (size_t)kN3D * Pst * sizeof(double2));
+            // ---- sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T.  The
+            // Norb x Norb block products run in fp32 (Gh rounded once from its
+            // binary64 sum over qz and taps); each neighbour's contribution is
+            // added to the binary64 sum over b.
+            float2 *scr = reinterpret_cast<float2 *>(sand);
+            float *ldsA = reinterpret_cast<float *>(sand + (size_t)kN3D * Pst * sizeof(float2));
             __syncthreads();  // the previous neighbour's sandwich reads are done
             const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
             for (int idx = tid; idx < kN3D * NN; idx += kBlock)
-                ldsA[idx] = Ag[idx];
-            double tr[kSR][kN3D], ti[kSR][kN3D];
+                ldsA[idx] = (float)Ag[idx];
+            float tr[kSR][kN3D], ti[kSR][kN3D];
 #pragma unroll
             for (int r = 0; r < kSR; ++r)
 #pragma unroll
                 for (int j = 0; j < kN3D; ++j) {
-                    tr[r][j] = 0.0;
-                    ti[r][j] = 0.0;
+                    tr[r][j] = 0.0f;
+                    ti[r][j] = 0.0f;
                 }
 #pragma unroll
             for (int i = 0; i < kN3D; ++i) {
@@ -374,20 +378,20 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                         const int ij = row >> 1;
                         if (ij < kNF && ij / kN3D == i && pval[t])
                             scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
-                                make_double2(acc[t][v], acc[t][v + 1]);
+                                make_float2((float)acc[t][v], (float)acc[t][v + 1]);
                     }
                 __syncthreads();
 #pragma unroll
                 for (int r = 0; r < kSR; ++r) {
                     const int base = pe[r] * NN + pn[r];
-                    const double *Arow = ldsA + i * NN + pm[r] * No;
+                    const float *Arow = ldsA + i * NN + pm[r] * No;
                     for (int l = 0; l < No; ++l) {
-                        const double am = Arow[l];
+                        const float am = Arow[l];
 #pragma unroll
                         for (int j = 0; j < kN3D; ++j) {
-                            const double2 sv = scr[j * Pst + base + l * No];
-                            tr[r][j] = fma(am, sv.x, tr[r][j]);
-                            ti[r][j] = fma(am, sv.y, ti[r][j]);
+                            const float2 sv = scr[j * Pst + base + l * No];
+                            tr[r][j] = fmaf(am, sv.x, tr[r][j]);
+                            ti[r][j] = fmaf(am, sv.y, ti[r][j]);
                         }
                     }
                 }
@@ -398,21 +402,24 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                 if (sval[r])
 #pragma unroll
                     for (int j = 0; j < kN3D; ++j)
-                        scr[j * Pst + spos[r]] = make_double2(tr[r][j], ti[r][j]);
+                        scr[j * Pst + spos[r]] = make_float2(tr[r][j], ti[r][j]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kSR; ++r) {
                 const int base = pe[r] * NN + pm[r] * No;
+                float ur = 0.0f, ui = 0.0f;
 #pragma unroll
                 for (int j = 0; j < kN3D; ++j) {
-                    const double *Arow = ldsA + j * NN + pn[r] * No;
+                    const float *Arow = ldsA + j * NN + pn[r] * No;
                     for (int l = 0; l < No; ++l) {
-                        const double2 sv = scr[j * Pst + base + l];
-                        const double am = Arow[l];
-                        sr[r] = fma(sv.x, am, sr[r]);
-                        si[r] = fma(sv.y, am, si[r]);
+                        const float2 sv = scr[j * Pst + base + l];
+                        const float am = Arow[l];
+                        ur = fmaf(sv.x, am, ur);
+                        ui = fmaf(sv.y, am, ui);
                     }
                 }
+                sr[r] += (double)ur;
+                si[r] += (double)ui;
             }
         }
         return wn;

@@ -45,6 +45,7 @@ constexpr size_t kZeroPage = mfmak::kZeroPage;
 constexpr size_t kAfragGroupBytes = mfmak::kAfragGroupBytes;
 constexpr size_t kSandBytes = mfmak::kSandBytes;
 constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
+constexpr int kDhR = (kN3D * 484 + kBlock - 1) / kBlock;  // dH values per thread (Norb <= 22)
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -55,6 +56,19 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
     if (bid >= (per << 3))
         return bid;
     return (bid & 7) * per + (bid >> 3);
+}
+
+// Workgroup barrier for data exchanged through LDS by ordinary LDS reads and
+// writes only: waits for this wave's LDS operations, not for its vector-memory
+// operations, so global -> LDS copies in flight into another buffer stay in
+// flight (a __syncthreads() fence would wait for them: they write LDS).  The
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 __device__ __forceinline__ uint32_t bf16_bits(float x)
@@ -165,20 +179,28 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
 #pragma unroll
     for (int t = 0; t < kNT; ++t)
         pval[t] = pos0 + 32 * t < P;
-    // sandwich positions of this thread
-    int spos[kSR], pe[kSR], pm[kSR], pn[kSR];
-    bool sval[kSR];
-#pragma unroll
-    for (int r = 0; r < kSR; ++r) {
-        spos[r] = tid + r * kBlock;
-        sval[r] = spos[r] < P;
-        if (!sval[r])
-            spos[r] = 0;
-        pe[r] = spos[r] / NN;
-        const int c = spos[r] - pe[r] * NN;
-        pm[r] = c / No;
-        pn[r] = c - pm[r] * No;
-    }
+    // Sandwich position r of this thread: pos = tid + r kBlock = (energy e,
+    // orbital pair (m, n)); pos 0 stands in for positions at or past P.
+    // Recomputed where used rather than kept live through the window loop (the
+    // empty asm keeps the compiler from hoisting it back out of the loop).
+    struct SPos {
+        int pos, e, m, n;
+        bool valid;
+    };
+    auto spos_of = [&](int r) {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        SPos q;
+        q.pos = t + r * kBlock;
+        q.valid = q.pos < P;
+        if (!q.valid)
+            q.pos = 0;
+        q.e = q.pos / NN;
+        const int c = q.pos - q.e * NN;
+        q.m = c / No;
+        q.n = c - q.m * No;
+        return q;
+    };
     double sr[kSR], si[kSR];
 #pragma unroll
     for (int r = 0; r < kSR; ++r) {
@@ -243,6 +265,7 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
     };
 
     double acc[kNT][10];
+    float dh[kDhR];  // this thread's share of the current neighbour's dH rows
     // window w from buf (its copies were issued earlier) while window wn is
     // copied into other; returns wn
     auto run_window = [&](int w, unsigned char *buf, unsigned char *other) {
@@ -250,6 +273,16 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
         const int wn = next_valid(w + 1);
         // window w has landed and every wave is done with the other buffer
         __syncthreads();
+        if (q == 0 && c == 0) {
+            // neighbour b's dH rows for its sandwich, loaded before any copy is
+            // issued behind them (vector-memory results return in order)
+            const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
+#pragma unroll
+            for (int r = 0; r < kDhR; ++r) {
+                const int idx = tid + r * kBlock;
+                dh[r] = idx < kN3D * NN ? (float)Ag[idx] : 0.0f;
+            }
+        }
         if (wn < nwin)
             issue(wn, other);
         if (q == 0 && c == 0) {
@@ -353,10 +386,17 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
             // added to the binary64 sum over b.
             float2 *scr = reinterpret_cast<float2 *>(sand);
             float *ldsA = reinterpret_cast<float *>(sand + (size_t)kN3D * Pst * sizeof(float2));
-            __syncthreads();  // the previous neighbour's sandwich reads are done
-            const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
-            for (int idx = tid; idx < kN3D * NN; idx += kBlock)
-                ldsA[idx] = (float)Ag[idx];
+            lds_barrier();  // the previous neighbour's sandwich reads are done
+#pragma unroll
+            for (int r = 0; r < kDhR; ++r) {
+                const int idx = tid + r * kBlock;
+                if (idx < kN3D * NN)
+                    ldsA[idx] = dh[r];
+            }
+            SPos sp[kSR];
+#pragma unroll
+            for (int r = 0; r < kSR; ++r)
+                sp[r] = spos_of(r);
             float tr[kSR][kN3D], ti[kSR][kN3D];
 #pragma unroll
             for (int r = 0; r < kSR; ++r)
@@ -368,7 +408,7 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
 #pragma unroll
             for (int i = 0; i < kN3D; ++i) {
                 if (i > 0)
-                    __syncthreads();
+                    lds_barrier();
                 // C rows held by this lane: row = 8 (v / 4) + 4 h + v % 4, row = 2 ij + re/im
 #pragma unroll
                 for (int t = 0; t < kNT; ++t)
@@ -380,11 +420,11 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                             scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
                                 make_float2((float)acc[t][v], (float)acc[t][v + 1]);
                     }
-                __syncthreads();
+                lds_barrier();
 #pragma unroll
                 for (int r = 0; r < kSR; ++r) {
-                    const int base = pe[r] * NN + pn[r];
-                    const float *Arow = ldsA + i * NN + pm[r] * No;
+                    const int base = sp[r].e * NN + sp[r].n;
+                    const float *Arow = ldsA + i * NN + sp[r].m * No;
                     for (int l = 0; l < No; ++l) {
                         const float am = Arow[l];
 #pragma unroll
@@ -396,21 +436,21 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int r = 0; r < kSR; ++r)
-                if (sval[r])
+                if (sp[r].valid)
 #pragma unroll
                     for (int j = 0; j < kN3D; ++j)
-                        scr[j * Pst + spos[r]] = make_float2(tr[r][j], ti[r][j]);
-            __syncthreads();
+                        scr[j * Pst + sp[r].pos] = make_float2(tr[r][j], ti[r][j]);
+            lds_barrier();
 #pragma unroll
             for (int r = 0; r < kSR; ++r) {
-                const int base = pe[r] * NN + pm[r] * No;
+                const int base = sp[r].e * NN + sp[r].m * No;
                 float ur = 0.0f, ui = 0.0f;
 #pragma unroll
                 for (int j = 0; j < kN3D; ++j) {
-                    const float *Arow = ldsA + j * NN + pn[r] * No;
+                    const float *Arow = ldsA + j * NN + sp[r].n * No;
                     for (int l = 0; l < No; ++l) {
                         const float2 sv = scr[j * Pst + base + l];
                         const float am = Arow[l];
@@ -439,10 +479,11 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
     float2 *Sk = (float2 *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
 #pragma unroll
     for (int r = 0; r < kSR; ++r) {
-        if (!sval[r])
+        const SPos q = spos_of(r);
+        if (!q.valid)
             continue;
-        const int c = spos[r] - pe[r] * NN;
-        Sk[(size_t)pe[r] * strideE + c] =
+        const int c = q.pos - q.e * NN;
+        Sk[(size_t)q.e * strideE + c] =
             make_float2((float)(p.alpha_re * sr[r] - p.alpha_im * si[r]),
                         (float)(p.alpha_re * si[r] + p.alpha_im * sr[r]));
     }
@@ -469,13 +510,13 @@ __global__ __launch_bounds__(kBlock, 1) void k_sse_mfma(const MfmaParams p)
     __shared__ __align__(16) unsigned char bufA[kBufBytes];
     __shared__ __align__(16) unsigned char bufB[kBufBytes];
     __shared__ __align__(16) unsigned char sand[kSandBytes];
+    // G: planar bf16 split (bf16x3) or complex64 (fp32); aux: zero page, A fragments
+    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
     int64_t L = xcd_remap(blockIdx.x, p.n_wg);
     const int k = (int)(L % p.Nkz);
     L /= p.Nkz;
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
-    // G: planar bf16 split (bf16x3) or complex64 (fp32); aux: zero page, A fragments
-    const TensorPtrs ptr{p.neigh, p.dH, p.G, nullptr, p.Sigma, p.afrag};
     mfma_tile<PREC>(ro(&p), ptr, a, k, et, bufA, bufB, sand);
 }
 

@@ -88,6 +88,11 @@ def ci95(xs):
     return 1.96 * statistics.stdev(xs) / math.sqrt(len(xs))
 
 
+def progress(msg):
+    """Progress lines go to stderr; stdout carries only the JSON result."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def cpu_baseline(prob, seed, target_s):
     """The oracle (unchanged) on a bounded sample of output blocks of the same
     workload: all k, sampled energies (incl. the edges) and atoms."""
@@ -277,6 +282,7 @@ def serving_section(args, torch, sse, configs, log):
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t0
         flops_plain += 2 * p.flops() * plain_iters
+        log(f"plain per-job: job NA={p.NA} NE={p.NE} Nw={p.Nw} done")
         del dp, ws, plan, hG, hS, hD
         torch.cuda.empty_cache()
     del stage
@@ -286,7 +292,7 @@ def serving_section(args, torch, sse, configs, log):
     # overlapping jobs
     serial = serving.Server(budget_bytes=200e9, slots=1, prec=sse.BF16X3, tol=1e-5)
     j0 = serving.make_jobs(probs, rate=1e9, seed=configs.SEED, iterations=plain_iters)
-    rs = serial.run(j0)
+    rs = serial.run(j0, log=log)
     ser = serving.summarize(rs)
     out["plain_per_job"] = {"tflops": round(plain_tflops, 3), "s": round(t_plain, 3),
                             "jobs": len(probs), "iterations_per_job": plain_iters,
@@ -333,7 +339,7 @@ def main():
         for i in range(args.warmup):
             step()
             if args.profile_steps:
-                print(f"prec {prec} warmup {i} done", flush=True)
+                progress(f"prec {prec} warmup {i} done")
         torch.cuda.synchronize()
         times = []
         t0 = time.perf_counter()
@@ -346,7 +352,7 @@ def main():
             e1.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
             if args.profile_steps:
-                print(f"prec {prec} step {i}: {times[-1]*1e3:.1f} ms", flush=True)
+                progress(f"prec {prec} step {i}: {times[-1]*1e3:.1f} ms")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         del dp, ws
@@ -360,7 +366,7 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written", flush=True)
+        progress(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
         torch.cuda.empty_cache()
     forms = [f for f in args.forms.split(",") if f]
@@ -381,7 +387,7 @@ def main():
                          "frac": round(tf / PEAK_MFMA_TFLOPS[name], 4),
                          "kernel": f"k_sse_mfma<{name}>"},
             "speedup_vs_fp64": None}
-        print(f"form {name}: {fm*1e3:.1f} ms/step", flush=True)
+        progress(f"form {name}: {fm*1e3:.1f} ms/step")
     if args.only and args.only != "fp64":
         print(json.dumps({"forms": form_out}), flush=True)
         return
@@ -420,7 +426,8 @@ def main():
     }
     for f in form_out.values():
         f["speedup_vs_fp64"] = round(med / (f["ms_per_step"] / 1e3), 2)
-    log = (lambda m: print(m, flush=True)) if args.profile_steps else (lambda m: None)
+    progress(f"fp64: {med*1e3:.1f} ms/step")
+    log = progress
     if args.only:
         args.batch, args.serving_jobs = "", 0
     if args.batch:
@@ -428,6 +435,7 @@ def main():
     if args.serving_jobs > 0:
         out["serving"] = serving_section(args, torch, sse, configs, log)
     if not args.no_cpu_baseline:
+        progress(f"cpu baseline: the oracle on a sample, about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(prob, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -184,7 +184,7 @@ def batch_section(args, torch, sse, configs, DeviceProblem, log):
             wave_s.append(e0.elapsed_time(e1) / 1e3)
             flops += sum(insts[i].flops() for i in wave)
             log(f"batch {name} wave {wi}: {len(wave)} instances, {wave_s[-1]:.3f} s")
-            if wi == 0 and name == "fp64":
+            if wi == 0:
                 # the same wave, one instance after the other (one-shot launches)
                 e0.record(stream)
                 for i, d in zip(wave, dps):

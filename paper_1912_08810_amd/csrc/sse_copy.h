@@ -9,6 +9,18 @@ namespace sse {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// x / d for 0 <= x < 2^20 and 1 <= d < 2^11, rd = 1 / d within an ulp: the
+// float product is within 2^20 (2^-23 + 2^-24) < 0.2 of x / d, so its
+// truncation is off by at most one and a single correction makes it exact.
+// (The integer division it replaces is a long instruction sequence on the GPU.)
+__device__ __forceinline__ int small_div(int x, int d, float rd)
+{
+    int q = (int)((float)x * rd);
+    const int r = x - q * d;
+    q += (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
+    return q;
+}
+
 // One lane's global -> LDS copy of U words (U = 4 or 1) to the wave's base d:
 // lane i's data lands at d + i U words.
 template <int U>
@@ -52,8 +64,9 @@ __device__ __forceinline__ void copy_window(uint32_t *dst, const uint32_t *g0, i
     const int n = nrow * upr;
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int dr = NT / upr, dc = NT - (NT / upr) * upr;
-    int r = tid / upr, c = tid - (tid / upr) * upr;
+    const float rupr = __builtin_amdgcn_rcpf((float)upr);
+    const int dr = small_div(NT, upr, rupr), dc = NT - dr * upr;
+    int r = small_div(tid, upr, rupr), c = tid - r * upr;
     for (int base = 0; base < n; base += NT) {
         uint32_t *d = dst + (size_t)(base + wv * 64) * U;
         if (base + tid < n) {

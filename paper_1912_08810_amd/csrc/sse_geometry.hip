@@ -48,6 +48,11 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     if (te_request > 0)
         TE = std::min(TE, te_request);
     TE = std::max(1, std::min(TE, NE));
+    // the sandwich's LDS region and output tiles per wave bound TE too (small
+    // Norb only: Norb >= 4 keeps TE = kPwg / Norb^2)
+    while (TE > 1 && (mfmak::sand_bytes(Norb, TE) > mfmak::kSandBytes ||
+                      mfmak::sand_tiles(Norb, TE) > 8 * mfmak::kSandT))
+        --TE;
     // A plane holds the window rows plus the reach of the columns past the
     // tile's last position: kPwg + (shift spread of the chunk) NN words; a
     // chunk's A fragments fill at most kMaxG groups.
@@ -74,7 +79,6 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     g.TE = TE;
     g.n_etiles = (NE + TE - 1) / TE;
     g.lds_win = (int)win_max;
-    g.lds_scr = kN3D * TE * NN;
     g.lds_bytes = 0;  // static LDS: two window buffers and the sandwich region
     return g;
 }

@@ -158,7 +158,6 @@ struct TileGeom {
     int TE;
     int n_etiles;
     int lds_win;     // window elements (complex128 for fp64, 8-byte for the MFMA path)
-    int lds_scr;     // complex128 elements of the sandwich scratch (MFMA path)
     size_t lds_bytes;
 };
 

@@ -12,8 +12,8 @@ namespace sse {
 // waves per SIMD); taps in groups of 8.  A window (one (b, q, tap chunk)) sits
 // in one of two LDS buffers: two planes of 32-bit words (bf16 hi and lo words,
 // or complex64 re/im interleaved across both), then the chunk's A fragments (at
-// most kMaxG groups of 64 lanes x 32 bytes).  The fp32 sandwich has its own
-// LDS region.  The MFMA workspace starts with a zero page (the copy source of
+// most kMaxG groups of 64 lanes x 32 bytes).  The sandwich (on the matrix
+// cores) has its own LDS region.  The MFMA workspace starts with a zero page (the copy source of
 // rows outside the energy grid), then the A fragments.
 namespace mfmak {
 constexpr int kBlock = 512;
@@ -26,8 +26,26 @@ constexpr int kMaxG = 5;
 constexpr size_t kAfragGroupBytes = 64 * 32;
 constexpr size_t kBufBytes = 2 * kPlaneBytes + kMaxG * kAfragGroupBytes;
 constexpr size_t kZeroPage = 256;
-// sandwich scratch: three planes of kPwg complex64, then dH rows as fp32 (Norb <= 22)
-constexpr size_t kSandBytes = 3 * (size_t)kPwg * 8 + 3 * 484 * 4;
+// Sandwich region (MFMA sandwich): two Kp x Ncolp fp32 matrices and Kp x Mp of
+// dH (Kp = 3 Norb rounded up to 4, Ncolp = 2 TE Norb rounded up to 16, Mp = 16
+// per 16 orbitals); the geometry keeps TE within it and within kSandT output
+// tiles of 16 x 16 per wave.  The two window buffers, this region and the
+// persistent kernel's tile slot fill the CU's 160 KiB.
+constexpr size_t kSandBytes = 160 * 1024 - 2 * kBufBytes - 256;
+constexpr int kSandT = 4;
+// LDS bytes of the sandwich region for Norb and TE
+constexpr size_t sand_bytes(int Norb, int TE)
+{
+    const size_t Kp = (size_t)((3 * Norb + 3) & ~3);
+    const size_t Ncolp = (size_t)((2 * TE * Norb + 15) & ~15);
+    const size_t Mp = (size_t)(16 * ((Norb + 15) >> 4));
+    return (2 * Kp * Ncolp + Kp * Mp) * 4;
+}
+// 16 x 16 output tiles of the sandwich for Norb and TE
+constexpr int sand_tiles(int Norb, int TE)
+{
+    return ((2 * TE * Norb + 15) >> 4) * ((Norb + 15) >> 4);
+}
 }  // namespace mfmak
 
 // Groups of eight consecutive taps of one chunk (the K extent of one MFMA
@@ -49,7 +67,6 @@ struct MfmaParams {
     int32_t TE, n_etiles;
     int64_t n_wg;
     int32_t lds_win;   // 8-byte elements of the window region
-    int32_t lds_scr;   // complex128 elements of the sandwich scratch region
     double alpha_re, alpha_im;
     TapTable taps;
     GroupTable groups;

@@ -1,6 +1,6 @@
 // sse_mfma.hip -- complex64-storage scattering self-energy on the gfx950
 // matrix cores: the (qz, w) tap filters of Eq. (3) (Sec. 2) as a GEMM on
-// MFMA, the dH sandwich as fp32 block products.
+// MFMA, then the dH sandwich as two fp32 GEMMs on MFMA.
 //
 // For one bond (a, b) with neighbour f, the tap sum
 //   Gh_ij[k, e, c] = sum_{q, w} Dt[q, w, a, b, i, j] G[(k - q) mod Nkz, e - s_w, f, c]
@@ -20,8 +20,9 @@
 //             operand x is split x = hi + lo (bf16 hi, bf16 lo = x - hi) and the
 //             product is hi*hi + hi*lo + lo*hi.
 // Accumulation: fp32 inside the MFMA over the taps of one energy window (one
-// qz row), binary64 across windows (the sum over qz and the tap chunks) and
-// over neighbours; the sandwich's Norb x Norb block products are fp32.
+// qz row), binary64 across windows (the sum over qz and the tap chunks); the
+// sandwich's Norb x Norb block products and the sum over neighbours are fp32
+// (v_mfma_f32_16x16x4f32).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,10 +45,11 @@ constexpr size_t kBufBytes = mfmak::kBufBytes;
 constexpr size_t kZeroPage = mfmak::kZeroPage;
 constexpr size_t kAfragGroupBytes = mfmak::kAfragGroupBytes;
 constexpr size_t kSandBytes = mfmak::kSandBytes;
-constexpr int kSR = kPwg / kBlock;            // sandwich positions per thread
 constexpr int kDhR = (kN3D * 484 + kBlock - 1) / kBlock;  // dH values per thread (Norb <= 22)
+constexpr int kSandT = mfmak::kSandT;         // sandwich output tiles per wave
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
@@ -153,7 +155,7 @@ __global__ void k_prep_afrag(const MfmaPrepParams p)
 // through two LDS buffers: while the MFMAs consume window n from one buffer,
 // the copy engine fills the other with window n + 1 (G rows and A fragments),
 // so one barrier per window separates them.  After the last window of a
-// neighbour the buffer just consumed holds the binary64 sandwich scratch.
+// neighbour the sandwich runs on the matrix cores in its own LDS region.
 // bufA and bufB are distinct __shared__ arrays and the window loop alternates
 // them by name, so the compiler can see that reads of one buffer do not
 // depend on the copies in flight into the other.
@@ -179,34 +181,36 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
 #pragma unroll
     for (int t = 0; t < kNT; ++t)
         pval[t] = pos0 + 32 * t < P;
-    // Sandwich position r of this thread: pos = tid + r kBlock = (energy e,
-    // orbital pair (m, n)); pos 0 stands in for positions at or past P.
-    // Recomputed where used rather than kept live through the window loop (the
-    // empty asm keeps the compiler from hoisting it back out of the loop).
-    struct SPos {
-        int pos, e, m, n;
-        bool valid;
-    };
-    auto spos_of = [&](int r) {
-        int t = tid;
-        asm volatile("" : "+v"(t));
-        SPos q;
-        q.pos = t + r * kBlock;
-        q.valid = q.pos < P;
-        if (!q.valid)
-            q.pos = 0;
-        q.e = q.pos / NN;
-        const int c = q.pos - q.e * NN;
-        q.m = c / No;
-        q.n = c - q.m * No;
-        return q;
-    };
-    double sr[kSR], si[kSR];
-#pragma unroll
-    for (int r = 0; r < kSR; ++r) {
-        sr[r] = 0.0;
-        si[r] = 0.0;
+    // Sandwich geometry (see the sandwich below): K = 3 Norb rounded up to the
+    // MFMA K step, Ncol = 2 TE Norb columns (energy, orbital, re/im) in tiles
+    // of 16, Norb rows in nmt tiles of 16.  LDS: G1 and B2 (Kp x Ncolp fp32
+    // each), then Ap (Kp x Mp).
+    const int Kp = (kN3D * No + 3) & ~3;
+    const int Ncol = 2 * p.TE * No;
+    const int Ncolp = (Ncol + 15) & ~15;
+    const int nmt = (No + 15) >> 4;
+    const int Mp = 16 * nmt;
+    const int nst = (Ncolp >> 4) * nmt;  // 16 x 16 output tiles
+    // one array indexed from its start (a short address chain keeps the
+    // compiler's knowledge that this region is not the window buffers)
+    float *sf = reinterpret_cast<float *>(sand);
+    const int oB2 = Kp * Ncolp, oAp = 2 * Kp * Ncolp;  // G1 at 0
+    // rows of G1 and B2 past 3 Norb and all of Ap start at zero (Ap's rows and
+    // columns past the data stay zero); the window barriers order this before
+    // the first sandwich
+    for (int idx = tid; idx < (Kp - kN3D * No) * Ncolp; idx += kBlock) {
+        sf[kN3D * No * Ncolp + idx] = 0.0f;
+        sf[oB2 + kN3D * No * Ncolp + idx] = 0.0f;
     }
+    for (int idx = tid; idx < Kp * Mp; idx += kBlock)
+        sf[oAp + idx] = 0.0f;
+    // Sigma tiles owned by this wave: s-th tile is wave + 8 s; their fp32 sums
+    // over neighbours
+    const float rNN = 1.0f / (float)NN, rNo = 1.0f / (float)No, r2No = 0.5f / (float)No;
+    f32x4 S2[kSandT];
+#pragma unroll
+    for (int st = 0; st < kSandT; ++st)
+        S2[st] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     const int64_t strideE = (int64_t)p.NA * NN;                 // elements per energy row
     const int64_t g_elems = (int64_t)p.Nkz * p.NE * strideE;
@@ -380,86 +384,94 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                 acc[t][v] += (double)C[t][v];
 
         if (q == p.Nqz - 1 && c == nch - 1) {
-            // ---- sandwich of neighbour b: Sigma += sum_ij dH_i Gh_ij dH_j^T.  The
-            // Norb x Norb block products run in fp32 (Gh rounded once from its
-            // binary64 sum over qz and taps); each neighbour's contribution is
-            // added to the binary64 sum over b.
-            float2 *scr = reinterpret_cast<float2 *>(sand);
-            float *ldsA = reinterpret_cast<float *>(sand + (size_t)kN3D * Pst * sizeof(float2));
+            // ---- sandwich of neighbour b on the matrix cores, fp32:
+            //   step 1, per j:  T_j[m, (e, n, x)] = sum_(i,l) Ap[(i,l), m] Gh_ij[e][l, n]_x
+            //   step 2:         S[n', (e, m, x)] += sum_(j,l) Ap[(j,l), n'] T_j[e][m, l]_x
+            // with Ap[(i, l), m] = dH_i[m, l] in both steps (x = re | im).
+            // v_mfma_f32_16x16x4f32: lane L holds A[L % 16][L / 16] and
+            // B[L / 16][L % 16] and receives C[4 (L / 16) + r][L % 16], r < 4.
             lds_barrier();  // the previous neighbour's sandwich reads are done
 #pragma unroll
             for (int r = 0; r < kDhR; ++r) {
-                const int idx = tid + r * kBlock;
-                if (idx < kN3D * NN)
-                    ldsA[idx] = dh[r];
-            }
-            SPos sp[kSR];
-#pragma unroll
-            for (int r = 0; r < kSR; ++r)
-                sp[r] = spos_of(r);
-            float tr[kSR][kN3D], ti[kSR][kN3D];
-#pragma unroll
-            for (int r = 0; r < kSR; ++r)
-#pragma unroll
-                for (int j = 0; j < kN3D; ++j) {
-                    tr[r][j] = 0.0f;
-                    ti[r][j] = 0.0f;
+                const int idx = tid + r * kBlock;  // dH_i[m, l], idx = i NN + m No + l
+                if (idx < kN3D * NN) {
+                    const int i = small_div(idx, NN, rNN), rem = idx - i * NN;
+                    const int m = small_div(rem, No, rNo), l = rem - m * No;
+                    sf[oAp + (i * No + l) * Mp + m] = dh[r];
                 }
+            }
+            // per-lane indices, made opaque here so that the compiler does not
+            // hoist them out of the window loop and hold them in registers
+            int ln = lane, pz = pos0;
+            asm volatile("" : "+v"(ln), "+v"(pz));
+            const int kr = ln >> 4, kc = ln & 15;
+            for (int j = 0; j < kN3D; ++j) {
+                // Gh_{.j} -> G1[(i, l), (e, n, x)]; C rows held by this lane:
+                // row = 8 (v / 4) + 4 h + v % 4 = 2 ij + x
 #pragma unroll
-            for (int i = 0; i < kN3D; ++i) {
-                if (i > 0)
-                    lds_barrier();
-                // C rows held by this lane: row = 8 (v / 4) + 4 h + v % 4, row = 2 ij + re/im
-#pragma unroll
-                for (int t = 0; t < kNT; ++t)
+                for (int t = 0; t < kNT; ++t) {
+                    const int pos = pz + 32 * t;
+                    const int e = small_div(pos, NN, rNN), rem = pos - e * NN;
+                    const int l = small_div(rem, No, rNo), n = rem - l * No;
+                    const int g1 = l * Ncolp + (e * No + n) * 2;
 #pragma unroll
                     for (int v = 0; v < 10; v += 2) {
                         const int row = 8 * (v >> 2) + 4 * h + (v & 3);
                         const int ij = row >> 1;
-                        if (ij < kNF && ij / kN3D == i && pval[t])
-                            scr[(ij % kN3D) * Pst + pos0 + 32 * t] =
+                        if (ij < kNF && ij % kN3D == j && pval[t])
+                            *reinterpret_cast<float2 *>(sf + g1 + (ij / kN3D) * No * Ncolp) =
                                 make_float2((float)acc[t][v], (float)acc[t][v + 1]);
                     }
+                }
                 lds_barrier();
+                // this wave's output tiles gt = wave + 8 st, the K steps outermost
+                // so that the tiles' MFMAs are independent
+                f32x4 T[kSandT];
 #pragma unroll
-                for (int r = 0; r < kSR; ++r) {
-                    const int base = sp[r].e * NN + sp[r].n;
-                    const float *Arow = ldsA + i * NN + sp[r].m * No;
-                    for (int l = 0; l < No; ++l) {
-                        const float am = Arow[l];
+                for (int st = 0; st < kSandT; ++st)
+                    T[st] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int ks = 0; ks < Kp; ks += 4) {
+                    const int ia = oAp + (ks + kr) * Mp + kc, ib = (ks + kr) * Ncolp + kc;
 #pragma unroll
-                        for (int j = 0; j < kN3D; ++j) {
-                            const float2 sv = scr[j * Pst + base + l * No];
-                            tr[r][j] = fmaf(am, sv.x, tr[r][j]);
-                            ti[r][j] = fmaf(am, sv.y, ti[r][j]);
+                    for (int st = 0; st < kSandT; ++st) {
+                        const int gt = wave + 8 * st;
+                        if (gt < nst) {
+                            const int ct = nmt == 1 ? gt : gt >> 1, mt = gt - ct * nmt;
+                            T[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                sf[ia + mt * 16], sf[ib + ct * 16], T[st], 0, 0, 0);
                         }
                     }
                 }
-            }
-            lds_barrier();
+                // T_j[m][col = (e, n, x)] -> B2[(j, n), (e, m, x)]
 #pragma unroll
-            for (int r = 0; r < kSR; ++r)
-                if (sp[r].valid)
+                for (int st = 0; st < kSandT; ++st) {
+                    const int gt = wave + 8 * st;
+                    if (gt < nst) {
+                        const int ct = nmt == 1 ? gt : gt >> 1, mt = gt - ct * nmt;
+                        const int col = ct * 16 + kc;
+                        const int e = small_div(col, 2 * No, r2No), rem = col - e * 2 * No;
+                        const int n = rem >> 1, x = rem & 1;
 #pragma unroll
-                    for (int j = 0; j < kN3D; ++j)
-                        scr[j * Pst + sp[r].pos] = make_float2(tr[r][j], ti[r][j]);
-            lds_barrier();
-#pragma unroll
-            for (int r = 0; r < kSR; ++r) {
-                const int base = sp[r].e * NN + sp[r].m * No;
-                float ur = 0.0f, ui = 0.0f;
-#pragma unroll
-                for (int j = 0; j < kN3D; ++j) {
-                    const float *Arow = ldsA + j * NN + sp[r].n * No;
-                    for (int l = 0; l < No; ++l) {
-                        const float2 sv = scr[j * Pst + base + l];
-                        const float am = Arow[l];
-                        ur = fmaf(sv.x, am, ur);
-                        ui = fmaf(sv.y, am, ui);
+                        for (int r = 0; r < 4; ++r) {
+                            const int m = mt * 16 + 4 * kr + r;
+                            if (m < No && col < Ncol)
+                                sf[oB2 + (j * No + n) * Ncolp + (e * No + m) * 2 + x] = T[st][r];
+                        }
                     }
                 }
-                sr[r] += (double)ur;
-                si[r] += (double)ui;
+                lds_barrier();  // G1 reads (and, after j = 2, the B2 writes) are done
+            }
+            for (int ks = 0; ks < Kp; ks += 4) {
+                const int ia = oAp + (ks + kr) * Mp + kc, ib = oB2 + (ks + kr) * Ncolp + kc;
+#pragma unroll
+                for (int st = 0; st < kSandT; ++st) {
+                    const int gt = wave + 8 * st;
+                    if (gt < nst) {
+                        const int ct = nmt == 1 ? gt : gt >> 1, mt = gt - ct * nmt;
+                        S2[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            sf[ia + mt * 16], sf[ib + ct * 16], S2[st], 0, 0, 0);
+                    }
+                }
             }
         }
         return wn;
@@ -476,16 +488,37 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
         w = run_window(w, bufB, bufA);
     }
 
-    float2 *Sk = (float2 *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
+    // ---- Sigma[k, e0 + e, a] = alpha * sum: the tiles S[n', (e, m, x)] go
+    // through LDS (G1 is free: every wave has passed the last sandwich's
+    // step 1) and are stored by position, coalesced
+    float *Sst = sf;
+    {
+        const int kr = lane >> 4, kc = lane & 15;
 #pragma unroll
-    for (int r = 0; r < kSR; ++r) {
-        const SPos q = spos_of(r);
-        if (!q.valid)
-            continue;
-        const int c = q.pos - q.e * NN;
-        Sk[(size_t)q.e * strideE + c] =
-            make_float2((float)(p.alpha_re * sr[r] - p.alpha_im * si[r]),
-                        (float)(p.alpha_re * si[r] + p.alpha_im * sr[r]));
+        for (int st = 0; st < kSandT; ++st) {
+            const int gt = wave + 8 * st;
+            if (gt < nst) {
+                const int ct = nmt == 1 ? gt : gt >> 1, mt = gt - ct * nmt;
+                const int col = ct * 16 + kc;
+                const int e = small_div(col, 2 * No, r2No), rem = col - e * 2 * No;
+                const int m = rem >> 1, x = rem & 1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = mt * 16 + 4 * kr + r;
+                    if (n < No && e < te)
+                        Sst[(e * NN + m * No + n) * 2 + x] = S2[st][r];
+                }
+            }
+        }
+    }
+    lds_barrier();
+    float2 *Sk = (float2 *)ptr.Sigma + ((size_t)k * p.NE + e0) * strideE + (size_t)a * NN;
+    for (int pos = tid; pos < P; pos += kBlock) {
+        const float sre = Sst[2 * pos], sim = Sst[2 * pos + 1];
+        const int e = small_div(pos, NN, rNN), c = pos - e * NN;
+        Sk[(size_t)e * strideE + c] =
+            make_float2((float)(p.alpha_re * sre - p.alpha_im * sim),
+                        (float)(p.alpha_re * sim + p.alpha_im * sre));
     }
 }
 

@@ -264,7 +264,6 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
             p.n_etiles = I.geom.n_etiles;
             p.n_wg = (int64_t)I.geom.n_etiles * d.Nkz * d.NA;
             p.lds_win = I.geom.lds_win;
-            p.lds_scr = I.geom.lds_scr;
             p.alpha_re = d.alpha_re;
             p.alpha_im = d.alpha_im;
             p.taps = I.taps;
@@ -316,7 +315,6 @@ MfmaParams mfma_params(const Instance &I)
     p.n_etiles = I.geom.n_etiles;
     p.n_wg = (int64_t)I.geom.n_etiles * d.Nkz * d.NA;
     p.lds_win = I.geom.lds_win;
-    p.lds_scr = I.geom.lds_scr;
     p.alpha_re = d.alpha_re;
     p.alpha_im = d.alpha_im;
     p.taps = I.taps;

@@ -1,5 +1,6 @@
 // sse_copy.h -- asynchronous global -> LDS copies (gfx950's global_load_lds)
-// used by the MFMA kernels to stage their G windows and A fragments.
+// used by the MFMA kernels to stage their G windows and A fragments, and the
+// small exact division shared by the kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -25,6 +25,7 @@
 #include <algorithm>
 
 #include "sse_internal.h"
+#include "sse_copy.h"
 
 namespace sse {
 
@@ -97,8 +98,11 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
     const size_t strideD = (size_t)p.NA * p.NB * kNF;  // one (q, w) slab of D~
     const size_t strideE = (size_t)p.NA * NN;          // one energy row of G
     // staging walk: element idx = tid + 256 it is (energy ew, channel cc)
-    const int st_e = kBlock / NN, st_c = kBlock - (kBlock / NN) * NN;
-    const int ew0 = tid / NN, cc0 = tid - (tid / NN) * NN;
+    // small_div: exact quotients of small integers without the GPU's long
+    // integer-division sequence
+    const float rNN = 1.0f / (float)NN, rNo = 1.0f / (float)No;
+    const int st_e = small_div(kBlock, NN, rNN), st_c = kBlock - st_e * NN;
+    const int ew0 = small_div(tid, NN, rNN), cc0 = tid - ew0 * NN;
 
     for (int b = 0; b < p.NB; ++b) {
         const int f = ro(ptr.neigh)[(size_t)a * p.NB + b];
@@ -220,8 +224,8 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int pos = tid + r * kBlock < P ? tid + r * kBlock : 0;
-                const int el = pos / NN, cpos = pos - el * NN;
-                const int m = cpos / No, n = cpos - m * No;
+                const int el = small_div(pos, NN, rNN), cpos = pos - el * NN;
+                const int m = small_div(cpos, No, rNo), n = cpos - m * No;
                 const int base = el * NN + n;
                 const double *Arow = ldsA + i * NN + m * No;
                 for (int l = 0; l < No; ++l) {
@@ -247,8 +251,8 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const int pos = tid + r * kBlock < P ? tid + r * kBlock : 0;
-            const int el = pos / NN, cpos = pos - el * NN;
-            const int m = cpos / No, n = cpos - m * No;
+            const int el = small_div(pos, NN, rNN), cpos = pos - el * NN;
+            const int m = small_div(cpos, No, rNo), n = cpos - m * No;
             const int base = el * NN + m * No;
 #pragma unroll
             for (int j = 0; j < kN3D; ++j) {
@@ -270,7 +274,7 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
         const int pos = tid + r * kBlock;
         if (pos >= P)
             continue;
-        const int el = pos / NN;
+        const int el = small_div(pos, NN, rNN);
         const int c = pos - el * NN;
         Sk[(size_t)el * strideE + c] = from_d2<T>(p.alpha_re * sr[r] - p.alpha_im * si[r],
                                                  p.alpha_re * si[r] + p.alpha_im * sr[r]);

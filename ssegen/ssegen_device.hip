@@ -40,22 +40,41 @@ __global__ void k_fill_antiherm(uint64_t seed, uint32_t stream, uint32_t scale_s
     }
 }
 
-// One wavefront per block: X <- X + 0.01 * (|X|_F / |N|_F) * N.
+// One wavefront per block: X <- X + 0.01 * (|X|_F / |N|_F) * N, N the
+// anti-Hermitian part of the block's raw complex normals.  The wave draws the
+// raw normals once into LDS (element (m, n) of N needs raw (m, n) and (n, m),
+// and both passes need N), then forms N from pairs: a quarter of the draws of
+// forming each element independently in each pass, with the same arithmetic
+// and summation order.
 template <typename T>
-__global__ void k_perturb(uint64_t seed, uint32_t st, int n_side, int64_t nblk, T *data)
+__global__ __launch_bounds__(256) void k_perturb(uint64_t seed, uint32_t st, int n_side,
+                                                 int64_t nblk, T *data)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t B = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (B >= nblk)
-        return;
+    extern __shared__ double2 raw_all[];  // 4 waves x n_side^2
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t B = blockIdx.x * (int64_t)(blockDim.x >> 6) + wv;
     const int nn = n_side * n_side;
+    double2 *raw = raw_all + (size_t)wv * nn;
+    const bool live = B < nblk;
+    if (live) {
+        const uint64_t base = (uint64_t)B * nn;
+        for (int e = lane; e < nn; e += 64) {
+            double re, im;
+            ssegen_cnormal(seed, base + (uint64_t)e, st, &re, &im);
+            raw[e] = make_double2(re, im);
+        }
+    }
+    __syncthreads();
+    if (!live)
+        return;
     T *x = data + (size_t)B * nn * 2;
-    const uint64_t base = (uint64_t)B * nn;
     double nx = 0.0, nr = 0.0;
     for (int e = lane; e < nn; e += 64) {
-        double re, im;
-        ssegen_antiherm(seed, base, n_side, e / n_side, e % n_side, st, &re, &im);
-        double xr = (double)x[2 * e], xi = (double)x[2 * e + 1];
+        const int m = e / n_side, n = e - m * n_side;
+        const double2 a = raw[e], b = raw[n * n_side + m];
+        /* X[m,n] - conj(X[n,m]) = (ar - br) + i (ai + bi), halved */
+        const double re = (a.x - b.x) * 0.5, im = (a.y + b.y) * 0.5;
+        const double xr = (double)x[2 * e], xi = (double)x[2 * e + 1];
         nx = nx + (xr * xr + xi * xi);
         nr = nr + (re * re + im * im);
     }
@@ -65,8 +84,9 @@ __global__ void k_perturb(uint64_t seed, uint32_t st, int n_side, int64_t nblk, 
     }
     const double f = nr > 0.0 ? 0.01 * (sqrt(nx) / sqrt(nr)) : 0.0;
     for (int e = lane; e < nn; e += 64) {
-        double re, im;
-        ssegen_antiherm(seed, base, n_side, e / n_side, e % n_side, st, &re, &im);
+        const int m = e / n_side, n = e - m * n_side;
+        const double2 a = raw[e], b = raw[n * n_side + m];
+        const double re = (a.x - b.x) * 0.5, im = (a.y + b.y) * 0.5;
         x[2 * e] = (T)((double)x[2 * e] + f * re);
         x[2 * e + 1] = (T)((double)x[2 * e + 1] + f * im);
     }
@@ -141,13 +161,16 @@ int ssegen_dev_perturb(uint64_t seed, int iteration, uint32_t stream_word, int n
     const int64_t nwg = (nblk + 3) / 4;
     if (nwg > 0x7fffffff)
         return (int)hipErrorInvalidValue;
+    const size_t lds = (size_t)4 * n_side * n_side * sizeof(double2);
+    if (lds > 64 * 1024)
+        return (int)hipErrorInvalidValue;
     if (fp32) {
         (void)hipGetLastError();
-        hipLaunchKernelGGL(k_perturb<float>, dim3((unsigned)nwg), dim3(256), 0,
+        hipLaunchKernelGGL(k_perturb<float>, dim3((unsigned)nwg), dim3(256), lds,
                            (hipStream_t)stream, seed, st, n_side, nblk, (float *)data);
     } else {
         (void)hipGetLastError();
-        hipLaunchKernelGGL(k_perturb<double>, dim3((unsigned)nwg), dim3(256), 0,
+        hipLaunchKernelGGL(k_perturb<double>, dim3((unsigned)nwg), dim3(256), lds,
                            (hipStream_t)stream, seed, st, n_side, nblk, (double *)data);
     }
     return (int)hipGetLastError();

@@ -123,6 +123,21 @@ def cpu_baseline(prob, seed, target_s):
     n = reps * len(blocks_all)
     per_block_alg = prob.flops() / (prob.Nkz * prob.NE * prob.NA)
     per_block_plain = prob.flops_plain() / (prob.Nkz * prob.NE * prob.NA)
+    # one core on a sixteenth of the sample, for the per-core rate
+    sub = blocks_all[::16]
+    t1 = time.perf_counter()
+    oracle.sigma(neigh, dH, Gb, D, prob.shifts(), prob.Nkz, prob.NE, blocks=sub, gslot=gslot,
+                 nthreads=1)
+    t1 = time.perf_counter() - t1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": round(per_block_alg * n / t / 1e9, 3),
         "unit": "GFLOP/s (algorithmic-equivalent)",
@@ -133,6 +148,9 @@ def cpu_baseline(prob, seed, target_s):
         "blocks_per_s": round(n / t, 2),
         "plain_gflops": round(per_block_plain * n / t / 1e9, 3),
         "extrapolated_full_job_s": round(t / n * prob.Nkz * prob.NE * prob.NA * 2, 1),
+        "one_core": {"value": round(per_block_alg * len(sub) / t1 / 1e9, 3),
+                     "blocks": len(sub), "s": round(t1, 2)},
+        "cpu_model": cpu_model,
     }
 
 

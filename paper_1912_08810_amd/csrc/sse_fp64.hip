@@ -67,6 +67,9 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double x, double y
     return make_float2((float)x, (float)y);
 }
 
+// Zero source of the window copies (rows outside the energy grid).
+__device__ __attribute__((aligned(16))) uint32_t g_zero16[4] = {0u, 0u, 0u, 0u};
+
 // One output tile: energies [et TE, et TE + TE) of (k, a).  pp supplies the
 // problem's sizes and tap table (a kernel argument or a batch table in global
 // memory), ptr its tensors.
@@ -131,7 +134,16 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                 const int wn = (te + smax - smin) * NN;
                 const int ebase = e0 - smax;
                 __syncthreads();
-                {
+                if constexpr (sizeof(T) == sizeof(double2)) {
+                    // complex128: the copy engine moves the rows straight into
+                    // LDS (16-byte units, rows outside the energy grid from a
+                    // zero block); the barrier below waits for it
+                    copy_window<4, kBlock>(reinterpret_cast<uint32_t *>(lds),
+                                           reinterpret_cast<const uint32_t *>(Gk),
+                                           (int64_t)strideE * 4, ebase, p.NE, te + smax - smin,
+                                           NN * 4, g_zero16);
+                } else {
+                    // complex64: promoted to binary64 on the way
                     int ew = ew0, cc = cc0;
                     for (int idx = tid; idx < wn; idx += kBlock) {
                         const int e = ebase + ew;

@@ -58,6 +58,18 @@ def test_orbital_counts(prec, Norb):
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("Norb,NE", [(1, 600), (2, 300), (4, 150), (17, 20), (21, 9)])
+def test_sandwich_tile_limits(prec, Norb, NE):
+    # small Norb with long energy grids: the energy tile is cut to what the
+    # sandwich's LDS region and output tiles hold; Norb > 16: two row tiles;
+    # every case ends in a ragged energy tile
+    prob = configs.Problem(NA=5, NB=3, Norb=Norb, Nkz=2, Nqz=2, NE=NE, Nw=7)
+    dp = gu.DeviceProblem(prob, 200 + Norb, fp32=True, scaled=True)
+    assert gu.run_sse(dp, prec=prec) == 0
+    check_full(dp, prec)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
 def test_general_alpha(prec):
     prob = configs.Problem(NA=11, NB=4, Norb=5, Nkz=3, Nqz=3, NE=19, Nw=5)
     dp = gu.DeviceProblem(prob, 21, fp32=True)

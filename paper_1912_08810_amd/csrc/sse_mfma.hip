@@ -359,7 +359,11 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
 #pragma unroll
                 for (int u = 0; u < kGS; ++u) {
                     const int t = tg + u;
-                    const int idx = 2 * (pos0 + (t < t1c ? (smax - p.taps.s[t]) * NN : 0));
+                    // one tap per instruction: the padding taps of a chunk's
+                    // last group are skipped (the first tap of a group is real)
+                    if (u > 0 && t >= t1c)
+                        break;
+                    const int idx = 2 * (pos0 + (smax - p.taps.s[t]) * NN);
 #pragma unroll
                     for (int tt = 0; tt < kNT; ++tt) {
                         const float bv = W[idx + 64 * tt];

@@ -163,19 +163,25 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                 // Taps in pairs: both taps' D~ values (scalar loads) and window
                 // reads are issued before one wait, then 2 x 36 FMAs per position.
                 // (complex64 storage keeps single taps: its conversions need the registers)
+                // The pair's (w, s) record was fetched during the previous pair,
+                // so the D~ loads and the window reads go out together.
                 int t = t0;
                 constexpr int kPair = sizeof(T) == sizeof(double2) ? 1 : 0;
+                int wa = p.tws[2 * t], sa = p.tws[2 * t + 1];
+                int wb = p.tws[2 * t + 2], sb = p.tws[2 * t + 3];
                 for (; kPair && t + 1 < t1; t += 2) {
-                    const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;
-                    const_ptr<T> dpb = Dq + (size_t)p.taps.w[t + 1] * strideD;
+                    const int nwa = p.tws[2 * t + 4], nsa = p.tws[2 * t + 5];
+                    const int nwb = p.tws[2 * t + 6], nsb = p.tws[2 * t + 7];
+                    const_ptr<T> dpa = Dq + (size_t)wa * strideD;
+                    const_ptr<T> dpb = Dq + (size_t)wb * strideD;
                     double2 da[kNF], db[kNF];
 #pragma unroll
                     for (int x = 0; x < kNF; ++x) {
                         da[x] = to_d2(dpa[x]);
                         db[x] = to_d2(dpb[x]);
                     }
-                    const double2 *wpa = lds + tid + (smax - p.taps.s[t]) * NN;
-                    const double2 *wpb = lds + tid + (smax - p.taps.s[t + 1]) * NN;
+                    const double2 *wpa = lds + tid + (smax - sa) * NN;
+                    const double2 *wpb = lds + tid + (smax - sb) * NN;
 #pragma unroll
                     for (int r = 0; r < kR; ++r) {
                         const double2 ga = wpa[r * kBlock];
@@ -187,6 +193,10 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                         for (int x = 0; x < kNF; ++x)
                             cmac(ar[r][x], ai[r][x], db[x].x, db[x].y, gb.x, gb.y);
                     }
+                    wa = nwa;
+                    sa = nsa;
+                    wb = nwb;
+                    sb = nsb;
                 }
                 for (; t < t1; ++t) {
                     const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;

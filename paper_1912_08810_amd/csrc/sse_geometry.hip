@@ -40,6 +40,16 @@ TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     return g;
 }
 
+void fill_tap_pairs(Fp64Params &p)
+{
+    for (int t = 0; t < 2 * kMaxTaps + 4; ++t)
+        p.tws[t] = 0;
+    for (int t = 0; t < p.taps.n; ++t) {
+        p.tws[2 * t] = p.taps.w[t];
+        p.tws[2 * t + 1] = p.taps.s[t];
+    }
+}
+
 TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out,
                        GroupTable *groups)
 {

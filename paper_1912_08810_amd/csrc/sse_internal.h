@@ -134,7 +134,13 @@ struct Fp64Params {
     int32_t lds_win;   // complex elements of the window / sandwich scratch region
     double alpha_re, alpha_im;
     TapTable taps;
+    // (w, s) of tap t at [2 t], [2 t + 1], padded: a tap pair's record is four
+    // consecutive words, fetched one pair ahead
+    int32_t tws[2 * kMaxTaps + 4];
 };
+
+// Fills Fp64Params::tws from Fp64Params::taps (host).
+void fill_tap_pairs(Fp64Params &p);
 
 
 // Sampled binary64 check of a complex64 result (sse_check.hip).

@@ -204,9 +204,9 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
     }
     for (int idx = tid; idx < Kp * Mp; idx += kBlock)
         sf[oAp + idx] = 0.0f;
+    const float rNN = 1.0f / (float)NN, rNo = 1.0f / (float)No, r2No = 0.5f / (float)No;
     // Sigma tiles owned by this wave: s-th tile is wave + 8 s; their fp32 sums
     // over neighbours
-    const float rNN = 1.0f / (float)NN, rNo = 1.0f / (float)No, r2No = 0.5f / (float)No;
     f32x4 S2[kSandT];
 #pragma unroll
     for (int st = 0; st < kSandT; ++st)

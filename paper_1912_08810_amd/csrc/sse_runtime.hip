@@ -220,6 +220,7 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
             p.alpha_re = d.alpha_re;
             p.alpha_im = d.alpha_im;
             p.taps = I.taps;
+            fill_tap_pairs(p);
             e = fp64_launch(p, d.prec == SSE_FP64C64, I.geom.lds_bytes, s);
             if (e != hipSuccess)
                 return hip_fail(e, "fp64 kernel launch");
@@ -296,6 +297,7 @@ Fp64Params fp64_params(const Instance &I)
     p.alpha_re = d.alpha_re;
     p.alpha_im = d.alpha_im;
     p.taps = I.taps;
+    fill_tap_pairs(p);
     return p;
 }
 

@@ -160,44 +160,61 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                     }
                 }
                 __syncthreads();
-                // Taps in pairs: both taps' D~ values (scalar loads) and window
-                // reads are issued before one wait, then 2 x 36 FMAs per position.
-                // (complex64 storage keeps single taps: its conversions need the registers)
-                // The pair's (w, s) record was fetched during the previous pair,
-                // so the D~ loads and the window reads go out together.
                 int t = t0;
-                constexpr int kPair = sizeof(T) == sizeof(double2) ? 1 : 0;
-                int wa = p.tws[2 * t], sa = p.tws[2 * t + 1];
-                int wb = p.tws[2 * t + 2], sb = p.tws[2 * t + 3];
-                for (; kPair && t + 1 < t1; t += 2) {
-                    const int nwa = p.tws[2 * t + 4], nsa = p.tws[2 * t + 5];
-                    const int nwb = p.tws[2 * t + 6], nsb = p.tws[2 * t + 7];
-                    const_ptr<T> dpa = Dq + (size_t)wa * strideD;
-                    const_ptr<T> dpb = Dq + (size_t)wb * strideD;
-                    double2 da[kNF], db[kNF];
-#pragma unroll
-                    for (int x = 0; x < kNF; ++x) {
-                        da[x] = to_d2(dpa[x]);
-                        db[x] = to_d2(dpb[x]);
-                    }
-                    const double2 *wpa = lds + tid + (smax - sa) * NN;
-                    const double2 *wpb = lds + tid + (smax - sb) * NN;
-#pragma unroll
-                    for (int r = 0; r < kR; ++r) {
-                        const double2 ga = wpa[r * kBlock];
-                        const double2 gb = wpb[r * kBlock];
+                if constexpr (sizeof(T) == sizeof(double2)) {
+                    // complex128: one tap at a time, its D~ (scalar loads) fetched
+                    // during the previous tap.  Scalar and LDS loads share one
+                    // wait counter and scalar loads complete out of order, so a
+                    // wait for window reads also waits for every scalar load in
+                    // flight; each tap therefore waits once (its window reads and
+                    // its D~, issued a tap earlier), then issues the next tap's
+                    // D~ before its 36 FMAs per position.  The scheduling barriers
+                    // keep the compiler from hoisting those loads above the wait.
+                    double2 dA[kNF], dB[kNF];
+                    int sh = p.tws[2 * t + 1], wn = p.tws[2 * t + 2];
+                    {
+                        const_ptr<T> dp = Dq + (size_t)p.tws[2 * t] * strideD;
 #pragma unroll
                         for (int x = 0; x < kNF; ++x)
-                            cmac(ar[r][x], ai[r][x], da[x].x, da[x].y, ga.x, ga.y);
-#pragma unroll
-                        for (int x = 0; x < kNF; ++x)
-                            cmac(ar[r][x], ai[r][x], db[x].x, db[x].y, gb.x, gb.y);
+                            dA[x] = to_d2(dp[x]);
                     }
-                    wa = nwa;
-                    sa = nsa;
-                    wb = nwb;
-                    sb = nsb;
+                    // tap t from cur while the D~ of tap t + 1 is fetched into nxt
+                    // (the table is padded, so the last tap fetches a valid block)
+                    auto step = [&](double2(&cur)[kNF], double2(&nxt)[kNF]) {
+                        const double2 *wp = lds + tid + (smax - sh) * NN;
+                        double2 g[kR];
+#pragma unroll
+                        for (int r = 0; r < kR; ++r)
+                            g[r] = wp[r * kBlock];
+                        const int sh2 = p.tws[2 * t + 3], wn2 = p.tws[2 * t + 4];
+                        __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+                        __builtin_amdgcn_sched_barrier(0);
+                        {
+                            const_ptr<T> dp = Dq + (size_t)wn * strideD;
+#pragma unroll
+                            for (int x = 0; x < kNF; ++x)
+                                nxt[x] = to_d2(dp[x]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int r = 0; r < kR; ++r)
+#pragma unroll
+                            for (int x = 0; x < kNF; ++x)
+                                cmac(ar[r][x], ai[r][x], cur[x].x, cur[x].y, g[r].x, g[r].y);
+                        sh = sh2;
+                        wn = wn2;
+                        ++t;
+                    };
+                    while (t + 1 < t1) {
+                        step(dA, dB);
+                        step(dB, dA);
+                    }
+                    if (t < t1)
+                        step(dA, dB);
                 }
+                // complex64: one tap at a time, loads then one wait (its
+                // conversions need the registers a prefetch would take)
                 for (; t < t1; ++t) {
                     const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;
                     double2 da[kNF];

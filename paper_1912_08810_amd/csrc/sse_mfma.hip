@@ -310,16 +310,20 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
             const uint4 A0 = Ab[gi * 128 + lane * 2];
             const uint4 A1 = Ab[gi * 128 + lane * 2 + 1];
             const int tg = p.groups.t0[g];
+            // the group's eight shifts, read unconditionally (the table is padded)
+            // so that they arrive together; padding taps (t >= t1c) read offset 0
+            int off[kGS];
+#pragma unroll
+            for (int u = 0; u < kGS; ++u) {
+                const int sv = p.taps.s[tg + u];
+                off[u] = (smax - sv) * NN * (int)(tg + u < t1c);  // no branch to sink the load into
+            }
             if constexpr (PREC == SSE_BF16X3) {
                 // lanes of half h carry taps tg + 4 h + u, u = 0..3
                 int idx[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int ta = tg + u, tb = tg + 4 + u;
-                    const int oa = ta < t1c ? (smax - p.taps.s[ta]) * NN : 0;
-                    const int ob = tb < t1c ? (smax - p.taps.s[tb]) * NN : 0;
-                    idx[u] = pos0 + (h ? ob : oa);
-                }
+                for (int u = 0; u < 4; ++u)
+                    idx[u] = pos0 + (h ? off[4 + u] : off[u]);
                 const bf16x8 ahi = __builtin_bit_cast(bf16x8, A0);
                 const bf16x8 alo = __builtin_bit_cast(bf16x8, A1);
                 // all four tiles' B operands first, then the three products in
@@ -363,7 +367,7 @@ __device__ __forceinline__ void mfma_tile(const_ptr<MfmaParams> pp, const Tensor
                     // last group are skipped (the first tap of a group is real)
                     if (u > 0 && t >= t1c)
                         break;
-                    const int idx = 2 * (pos0 + (smax - p.taps.s[t]) * NN);
+                    const int idx = 2 * (pos0 + off[u]);
 #pragma unroll
                     for (int tt = 0; tt < kNT; ++tt) {
                         const float bv = W[idx + 64 * tt];

@@ -51,8 +51,8 @@ constexpr int kNF = kN3D * kN3D;  // (i, j) filters
 struct TapTable {
     int32_t n;
     int32_t nchunk;
-    int32_t w[kMaxTaps];
-    int32_t s[kMaxTaps];
+    int32_t w[kMaxTaps + 8];  // padded by one group of 8 (zeros) so that a
+    int32_t s[kMaxTaps + 8];  // group's entries can be read unconditionally
     int32_t cb[kMaxTaps + 1];
 };
 

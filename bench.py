@@ -57,7 +57,8 @@ def parse():
 # traffic is reported as null.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sse_fp64_device_scale_traffic.json")
 KERNEL_SOURCES = ["paper_1912_08810_amd/csrc/sse_fp64.hip",
-                  "paper_1912_08810_amd/csrc/sse_internal.h"]
+                  "paper_1912_08810_amd/csrc/sse_internal.h",
+                  "paper_1912_08810_amd/csrc/sse_copy.h"]
 
 
 def kernel_sources_sha256():

@@ -10,6 +10,11 @@ namespace sse {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8) that waits for lgkmcnt to reach 0 (LDS and scalar
+// memory) and leaves vmcnt and expcnt at their maxima, i.e. not waited for.
+constexpr unsigned kWaitLgkm0 = 0xC07F;
+
 // x / d for 0 <= x < 2^20 and 1 <= d < 2^11, rd = 1 / d within an ulp: the
 // float product is within 2^20 (2^-23 + 2^-24) < 0.2 of x / d, so its
 // truncation is off by at most one and a single correction makes it exact.

@@ -188,7 +188,7 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                             g[r] = wp[r * kBlock];
                         const int sh2 = p.tws[2 * t + 3], wn2 = p.tws[2 * t + 4];
                         __builtin_amdgcn_sched_barrier(0);
-                        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+                        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
                         __builtin_amdgcn_sched_barrier(0);
                         {
                             const_ptr<T> dp = Dq + (size_t)wn * strideD;

@@ -68,7 +68,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
 __device__ __forceinline__ void lds_barrier()
 {
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // vmcnt and expcnt not waited
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }

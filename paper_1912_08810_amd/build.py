@@ -12,8 +12,12 @@ LIB = os.path.join(PKG, "libsse.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed fp32 VALU ops stay off: hipcc would otherwise form them from float2 code.
+# The atomic optimizer stays off too: the persistent kernels' tile pull is a
+# single-lane atomic whose result is needed only when the current tile ends, and
+# the optimizer's wave-reduced form reads the result back at once.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
              "-Wno-unused-command-line-argument"]
 
 

@@ -267,6 +267,9 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                 const int m = small_div(cpos, No, rNo), n = cpos - m * No;
                 const int base = el * NN + n;
                 const double *Arow = ldsA + i * NN + m * No;
+                // unrolled explicitly: inlined into the persistent kernel's
+                // loop the compiler's own heuristics leave it rolled
+#pragma unroll 4
                 for (int l = 0; l < No; ++l) {
                     const double am = Arow[l];
 #pragma unroll
@@ -296,6 +299,7 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
 #pragma unroll
             for (int j = 0; j < kN3D; ++j) {
                 const double *Arow = ldsA + j * NN + n * No;
+#pragma unroll 8
                 for (int l = 0; l < No; ++l) {
                     const double2 s = lds[j * Pst + base + l];
                     const double am = Arow[l];
@@ -334,17 +338,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
 }
 
 // Persistent form: a fixed grid pulls tiles from the batch's work queues
-// (one queue per XCD, then the others) until all are taken.
+// (one queue per XCD, then the others) until all are taken; the next tile's
+// ticket is taken while the current tile runs.
 template <typename T>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLaunch bl)
 {
     extern __shared__ double2 lds[];
-    __shared__ int s_tile[4];
+    __shared__ int s_tile[4], s_st[2];
     const int home = blockIdx.x & 7;
+    if (threadIdx.x == 0)
+        pull_first(bl, home, s_st, s_tile);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0)
-            batch_pull(bl, home, s_tile);
-        __syncthreads();
         const int inst = __builtin_amdgcn_readfirstlane(s_tile[0]);
         const int a = __builtin_amdgcn_readfirstlane(s_tile[1]);
         const int k = __builtin_amdgcn_readfirstlane(s_tile[2]);
@@ -352,8 +357,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLa
         __syncthreads();
         if (inst < 0)
             break;
+        long long ticket = 0;
+        if (threadIdx.x == 0)
+            ticket = pull_take(bl, home, s_st);
         fp64_tile<T>(ro(reinterpret_cast<const Fp64Params *>(bl.params)) + inst, bl.ptr[inst], a,
                      k, et, lds);
+        if (threadIdx.x == 0)
+            pull_resolve(bl, home, ticket, s_st, s_tile);
+        __syncthreads();
     }
 }
 

@@ -86,37 +86,73 @@ struct BatchLaunch {
     TensorPtrs ptr[kMaxBatch];
 };
 
-// Thread 0 of a workgroup takes the next tile: its home queue first, then the
-// others.  s_tile = (instance, atom, k, energy tile), instance -1 when all
-// queues are empty.
-__device__ __forceinline__ void batch_pull(const BatchLaunch &bl, int home, int *s_tile)
+// Tile pulls of the persistent kernels, done by thread 0 of a workgroup: its
+// home queue first, then the others.  A ticket (a queue-local tile index) is
+// taken with one atomic when the previous tile starts, so the atomic's latency
+// hides under that tile, and turned into a tile when it ends.  st[0] = queues
+// given up so far (the current queue is (home + st[0]) % kQueues), st[1] = the
+// chunk of this workgroup's previous ticket in the current queue, -1 if none.
+// A workgroup's tickets from one queue increase, so the chunk search starts at
+// st[1]; the common case, the same chunk or the next, costs one or two loads.
+
+// Ticket of the current queue; counts past the queue's end are harmless.  (The
+// library is built with the compiler's atomic optimizer off: it would rewrite
+// this single-lane atomic into a wave-reduced one and await its result at once.)
+__device__ __forceinline__ long long pull_take(const BatchLaunch &bl, int home, const int *st)
 {
-    for (int d = 0; d < kQueues; ++d) {
+    return (long long)atomicAdd(&bl.counters[(home + st[0]) & (kQueues - 1)], 1ULL);
+}
+
+// s_tile = (instance, atom, k, energy tile) of ticket t, or instance -1 once
+// every queue is exhausted; a ticket past its queue's end moves on to the next
+// queue (there the ticket is taken and awaited here).
+__device__ __forceinline__ void pull_resolve(const BatchLaunch &bl, int home, long long t, int *st,
+                                             int *s_tile)
+{
+    for (int d = st[0]; d < kQueues;) {
         const int qx = (home + d) & (kQueues - 1);
-        if (bl.qcount[qx] == 0)
-            continue;
-        const long long t = (long long)atomicAdd(&bl.counters[qx], 1ULL);
-        if (t >= bl.qcount[qx])
-            continue;
-        int lo = bl.qbeg[qx], hi = bl.qbeg[qx + 1] - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (bl.chunk_start[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
+        if (t < bl.qcount[qx]) {
+            int lo = st[1] >= 0 ? st[1] : bl.qbeg[qx];
+            int hi = bl.qbeg[qx + 1] - 1;
+            // chunk_start[lo] <= t; the chunk of t is the last such index
+            if (lo < hi && bl.chunk_start[lo + 1] <= t) {
+                ++lo;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (bl.chunk_start[mid] <= t)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+            }
+            st[0] = d;
+            st[1] = lo;
+            const int inst = bl.chunk_inst[lo];
+            const long long rem = t - bl.chunk_start[lo];
+            const int nkz = bl.nkz[inst];
+            s_tile[0] = inst;
+            s_tile[1] = bl.chunk_atom[lo];
+            s_tile[2] = (int)(rem % nkz);
+            s_tile[3] = (int)(rem / nkz);
+            return;
         }
-        const int inst = bl.chunk_inst[lo];
-        const long long rem = t - bl.chunk_start[lo];
-        const int nkz = bl.nkz[inst];
-        s_tile[0] = inst;
-        s_tile[1] = bl.chunk_atom[lo];
-        s_tile[2] = (int)(rem % nkz);
-        s_tile[3] = (int)(rem / nkz);
-        return;
+        ++d;
+        st[0] = d;
+        st[1] = -1;
+        if (d < kQueues)
+            t = bl.qcount[(home + d) & (kQueues - 1)] > 0 ? pull_take(bl, home, st) : 0;
     }
     s_tile[0] = -1;
     s_tile[1] = s_tile[2] = s_tile[3] = 0;
+}
+
+// Thread 0's first pull: the home queue's first ticket, resolved.
+__device__ __forceinline__ void pull_first(const BatchLaunch &bl, int home, int *st, int *s_tile)
+{
+    st[0] = 0;
+    st[1] = -1;
+    const long long t = bl.qcount[home] > 0 ? pull_take(bl, home, st) : 0;
+    pull_resolve(bl, home, t, st, s_tile);
 }
 
 // Launch parameters of the FP64 tiled kernel (one component).  G, D and Sigma

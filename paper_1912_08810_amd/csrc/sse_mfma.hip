@@ -561,19 +561,19 @@ __global__ __launch_bounds__(kBlock, 1) void k_sse_mfma(const MfmaParams p)
     mfma_tile<PREC>(ro(&p), ptr, a, k, et, bufA, bufB, sand);
 }
 
-// Persistent form over a batch's work queues (see batch_pull).
+// Persistent form over a batch's work queues (see pull_resolve).
 template <int PREC>
 __global__ __launch_bounds__(kBlock, 1) void k_sse_mfma_persistent(const BatchLaunch bl)
 {
     __shared__ __align__(16) unsigned char bufA[kBufBytes];
     __shared__ __align__(16) unsigned char bufB[kBufBytes];
     __shared__ __align__(16) unsigned char sand[kSandBytes];
-    __shared__ int s_tile[4];
+    __shared__ int s_tile[4], s_st[2];
     const int home = blockIdx.x & 7;
+    if (threadIdx.x == 0)
+        pull_first(bl, home, s_st, s_tile);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0)
-            batch_pull(bl, home, s_tile);
-        __syncthreads();
         const int inst = __builtin_amdgcn_readfirstlane(s_tile[0]);
         const int a = __builtin_amdgcn_readfirstlane(s_tile[1]);
         const int k = __builtin_amdgcn_readfirstlane(s_tile[2]);
@@ -581,8 +581,14 @@ __global__ __launch_bounds__(kBlock, 1) void k_sse_mfma_persistent(const BatchLa
         __syncthreads();
         if (inst < 0)
             break;
+        long long ticket = 0;
+        if (threadIdx.x == 0)
+            ticket = pull_take(bl, home, s_st);
         mfma_tile<PREC>(ro(reinterpret_cast<const MfmaParams *>(bl.params)) + inst, bl.ptr[inst],
                         a, k, et, bufA, bufB, sand);
+        if (threadIdx.x == 0)
+            pull_resolve(bl, home, ticket, s_st, s_tile);
+        __syncthreads();
     }
 }
 

@@ -40,6 +40,21 @@ int main() {
   printf("batch poll %d\n", sse_wait(tb));
   sse_plan_destroy(pb);
   {
+    // binary64 batch of 3 + 2 atoms: three of the eight work queues stay empty
+    sse_desc e[2] = {d, d};
+    for (auto &x : e) { x.prec = SSE_FP64; x.ncomp = 1; x.NA = 3; }
+    e[1].NA = 2; e[1].NE = 9;
+    const int32_t *she[2] = {sh, sh};
+    sse_plan_t pe; size_t wse;
+    if (sse_plan_batch(e, she, 2, &pe, &wse)) { printf("batch64: %s\n", sse_last_error()); return 1; }
+    std::vector<char> WE(wse);
+    sse_args ae[2] = {a, a};
+    uint64_t te;
+    if (sse_submit(pe, ae, WE.data(), wse, nullptr, &te)) { printf("bsubmit64 %s\n", sse_last_error()); return 1; }
+    if (sse_wait(te)) return 5;
+    sse_plan_destroy(pe);
+  }
+  {
     uint64_t ta, tb2;
     if (sse_submit(p2, &a, W.data(), ws, nullptr, &ta)) return 2;
     if (sse_poll(ta) != SSE_PENDING) return 3;

@@ -2,15 +2,93 @@
 // the real wrappers towards the runtime: the status word is cleared, the check
 // sums get known values (|diff|^2 = 1e-12, |ref|^2 = 1), and every launch
 // reports hipGetLastError() as the real launches do.
+//
+// The persistent launchers run the kernels' own tile-pull code (pull_first,
+// pull_take, pull_resolve) for a grid of simulated workgroups, each taking its
+// next ticket when a tile starts and resolving it when the tile ends, in a
+// scrambled interleaving, for several grid sizes; every tile of every
+// instance must come out exactly once and every workgroup must finish.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
 #include "sse_internal.h"
 #include "sse_mfma.h"
 namespace sse {
+template <typename Params>
+static void simulate_pulls(const BatchLaunch &bl0, int n_inst, int grid)
+{
+    BatchLaunch bl = bl0;
+    const Params *P = static_cast<const Params *>(bl.params);
+    std::vector<long long> base(n_inst + 1, 0);
+    for (int t = 0; t < n_inst; ++t)
+        base[t + 1] = base[t] + (long long)P[t].NA * bl.nkz[t] * P[t].n_etiles;
+    std::vector<int> seen(base[n_inst], 0);
+    for (int x = 0; x < kQueues; ++x)
+        bl.counters[x] = 0;
+    struct Wg { int st[2], tile[4]; long long ticket; int phase; };  // phase 0 start, 1 in tile, 2 done
+    std::vector<Wg> wg(grid);
+    for (int g = 0; g < grid; ++g) {
+        pull_first(bl, g & 7, wg[g].st, wg[g].tile);
+        wg[g].phase = 0;
+    }
+    unsigned rng = 12345u + grid;
+    int live = grid;
+    while (live > 0) {
+        rng = rng * 1664525u + 1013904223u;
+        Wg &w = wg[(rng >> 8) % grid];
+        const int home = (int)(&w - wg.data()) & 7;
+        if (w.phase == 2)
+            continue;
+        if (w.phase == 0) {
+            const int inst = w.tile[0];
+            if (inst < 0) {
+                w.phase = 2;
+                --live;
+                continue;
+            }
+            const int a = w.tile[1], k = w.tile[2], et = w.tile[3];
+            if (inst >= n_inst || a < 0 || a >= P[inst].NA || k < 0 || k >= bl.nkz[inst] || et < 0 ||
+                et >= P[inst].n_etiles) {
+                printf("pull: tile out of range (%d %d %d %d)\n", inst, a, k, et);
+                std::abort();
+            }
+            ++seen[base[inst] + ((long long)a * P[inst].n_etiles + et) * bl.nkz[inst] + k];
+            w.ticket = pull_take(bl, home, w.st);
+            w.phase = 1;
+        } else {
+            pull_resolve(bl, home, w.ticket, w.st, w.tile);
+            w.phase = 0;
+        }
+    }
+    for (size_t i = 0; i < seen.size(); ++i)
+        if (seen[i] != 1) {
+            printf("pull: grid %d, tile %zu taken %d times\n", grid, i, seen[i]);
+            std::abort();
+        }
+}
+template <typename Params>
+static void check_pulls(const BatchLaunch &bl, int grid)
+{
+    int n_inst = 0;
+    while (n_inst < kMaxBatch && bl.ptr[n_inst].Sigma != nullptr)
+        ++n_inst;
+    for (int g : {1, 3, 8, 13, 64, grid})
+        simulate_pulls<Params>(bl, n_inst, g);
+}
 hipError_t fp64_launch(const Fp64Params &, bool, size_t, hipStream_t) { return hipSuccess; }
-hipError_t fp64_persistent_launch(const BatchLaunch &, bool, int, size_t, hipStream_t) { return hipSuccess; }
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool, int grid, size_t, hipStream_t)
+{
+    check_pulls<Fp64Params>(bl, grid);
+    return hipSuccess;
+}
 hipError_t mfma_prep_launch(int, const MfmaPrepParams &, hipStream_t) { return hipSuccess; }
 hipError_t mfma_split_launch(const float2 *, void *, int64_t, hipStream_t) { return hipGetLastError(); }
 hipError_t mfma_launch(int, const MfmaParams &, size_t, hipStream_t) { return hipSuccess; }
-hipError_t mfma_persistent_launch(int, const BatchLaunch &, int, size_t, hipStream_t) { return hipSuccess; }
+hipError_t mfma_persistent_launch(int, const BatchLaunch &bl, int grid, size_t, hipStream_t)
+{
+    check_pulls<MfmaParams>(bl, grid);
+    return hipSuccess;
+}
 hipError_t launch_clear_status(uint32_t *s, hipStream_t) { *s = 0; return hipGetLastError(); }
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t) { for (int i = 0; i < n; ++i) p[i] = 0; return hipSuccess; }
 hipError_t launch_validate_neigh(const int32_t *, int64_t, int32_t, uint32_t *, hipStream_t) { return hipSuccess; }

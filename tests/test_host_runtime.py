@@ -3,7 +3,10 @@ batch tables) under AddressSanitizer and UBSan, on the CPU: it is built with
 g++ from the library's own sources against a stand-in HIP header and stub
 launchers (tests/host_runtime/), and driven through the C ABI.  Includes the
 regression test for polling: a pending sse_poll must not make the next
-submission report a launch failure."""
+submission report a launch failure.  The persistent launchers' stand-ins run
+the kernels' tile-pull code for simulated workgroups in a scrambled order
+(grids of 1 to the plan's size, batches that leave work queues empty): every
+tile must come out exactly once."""
 import os
 import subprocess
 

@@ -53,12 +53,13 @@ def parse():
 
 # HBM traffic of the binary64 kernel, from the FETCH_SIZE / WRITE_SIZE counter
 # passes summarised under profiles/.  The summary records a hash of the kernel's
-# sources; once they change, the counters no longer describe the kernel and the
-# traffic is reported as null.
+# sources and of the build script (its compile flags); once they change, the
+# counters no longer describe the kernel and the traffic is reported as null.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sse_fp64_device_scale_traffic.json")
 KERNEL_SOURCES = ["paper_1912_08810_amd/csrc/sse_fp64.hip",
                   "paper_1912_08810_amd/csrc/sse_internal.h",
-                  "paper_1912_08810_amd/csrc/sse_copy.h"]
+                  "paper_1912_08810_amd/csrc/sse_copy.h",
+                  "paper_1912_08810_amd/build.py"]
 
 
 def kernel_sources_sha256():

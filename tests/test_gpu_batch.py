@@ -74,3 +74,23 @@ def test_batch_of_one_and_bad_neighbour_in_batch():
     bad[0, 0] = dps[1].prob.NA + 5
     dps[1].neigh.copy_(__import__("torch").from_numpy(bad))
     assert run_batch(dps, 0) == sse.ERR_NEIGH
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batch_with_empty_work_queues(prec):
+    """Five atoms in all: three of the eight work queues are empty, so the
+    workgroups that start on them move on to the others at once."""
+    fp32 = prec != 0
+    probs = [configs.Problem(NA=3, NB=2, Norb=5, Nkz=3, Nqz=2, NE=23, Nw=6),
+             configs.Problem(NA=2, NB=1, Norb=5, Nkz=4, Nqz=3, NE=17, Nw=4)]
+    dps = [gu.DeviceProblem(p, 500 + i, ncomp=1, fp32=fp32, scaled=fp32)
+           for i, p in enumerate(probs)]
+    assert run_batch(dps, prec, tile_e=[2, 3]) == 0
+    for i, dp in enumerate(dps):
+        e = gu.rel_fro(dp.sigma_host(0), gu.oracle_full(dp, 0))
+        print(f"  inst {i} {dp.prob}: rel_fro={e:.3e}", flush=True)
+        assert e <= TOL[prec]
+        batched = dp.Sigma.clone()
+        dp.Sigma.fill_(float("nan"))
+        assert gu.run_sse(dp, prec=prec, tile_e=[2, 3][i]) == 0
+        assert bool((batched == dp.Sigma).all()), i

@@ -4,7 +4,9 @@
 One step = one sse_compute of the device-scale problem (NA=1024, NB=4,
 Norb=10, Nkz=Nqz=7, NE=1000, Nw=30; Sigma [7, 1000, 1024, 10, 10]) for both
 components (lesser and greater) in binary64, inputs resident in HBM.  Prints
-one JSON line; see the design doc for the flop and byte accounting.
+one JSON line.  Algorithmic flops per launch: 8 N3D^2 Norb^2 per (k, e, q, w,
+a, b) for the tap correlation plus 48 Norb^3 per (k, e, a, b) for the dH
+sandwich, 4.4730e13 at this size.
 """
 from __future__ import annotations
 
@@ -333,8 +335,8 @@ def serving_section(args, torch, sse, configs, log):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
-              "(every output block is independent; see DESIGN.md for how the path shards).",
+        print("bench.py: one GPU only; --gpus above 1 is not supported (every output "
+              "block is independent, so a multi-GPU run would split the atoms across GPUs).",
               file=sys.stderr)
         sys.exit(2)
     import torch

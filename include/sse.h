@@ -61,7 +61,7 @@ typedef enum {
     SSE_ERR_BUSY = 6,       /* too many submissions in flight */
     SSE_ERR_TOLERANCE = 7,  /* sse_check: sampled error above the caller's tolerance */
     SSE_ERR_DEVICE = 8,     /* a HIP runtime call failed (the text names it) */
-    SSE_ERR_UNSUPPORTED = 9 /* valid request that this build does not implement */
+    SSE_ERR_UNSUPPORTED = 9 /* valid request that this library does not implement */
 } sse_status;
 
 typedef enum {

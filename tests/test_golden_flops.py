@@ -3,7 +3,7 @@ the reading of its flop formulas: OMEN's 64 NA NB N3D Nkz Nqz NE Nw Norb^3
 reproduces the table with Nqz = Nkz and Norb = 12 (the value the table implies;
 Norb is not printed) to 0.1%.  The data-centric formula 32 (...) Norb^3 +
 32 NA NB N3D Nkz NE Norb^3 comes out 0.3-1.0% below its row, which is
-recorded here as the tolerance.  The same test checks this build's own
+recorded here as the tolerance.  The same test checks the library's own
 per-component count of the reassociated form against a direct operation count."""
 import json
 import os

@@ -93,7 +93,8 @@ struct BatchLaunch {
 // given up so far (the current queue is (home + st[0]) % kQueues), st[1] = the
 // chunk of this workgroup's previous ticket in the current queue, -1 if none.
 // A workgroup's tickets from one queue increase, so the chunk search starts at
-// st[1]; the common case, the same chunk or the next, costs one or two loads.
+// st[1]: a ticket in the same chunk costs one load, one in the next chunk two,
+// and only a ticket further on (or the first in a queue) a binary search.
 
 // Ticket of the current queue; counts past the queue's end are harmless.  (The
 // library is built with the compiler's atomic optimizer off: it would rewrite
@@ -114,9 +115,14 @@ __device__ __forceinline__ void pull_resolve(const BatchLaunch &bl, int home, lo
         if (t < bl.qcount[qx]) {
             int lo = st[1] >= 0 ? st[1] : bl.qbeg[qx];
             int hi = bl.qbeg[qx + 1] - 1;
-            // chunk_start[lo] <= t; the chunk of t is the last such index
-            if (lo < hi && bl.chunk_start[lo + 1] <= t) {
+            // chunk_start[lo] <= t; the chunk of t is the last such index:
+            // step over at most two chunks, then search the rest
+            int steps = 0;
+            while (steps < 2 && lo < hi && bl.chunk_start[lo + 1] <= t) {
                 ++lo;
+                ++steps;
+            }
+            if (steps == 2) {
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (bl.chunk_start[mid] <= t)

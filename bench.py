@@ -34,8 +34,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16x3",
-                    help="precision forms timed after the binary64 headline ('' = none)")
+    ap.add_argument("--forms", default="fp32,bf16x3,fp64c64",
+                    help="precision forms timed after the binary64 headline ('' = none); "
+                         "fp64c64 = binary64 arithmetic on complex64 storage")
     ap.add_argument("--only", default="",
                     help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
     ap.add_argument("--batch", default="fp64,bf16x3",
@@ -396,19 +397,25 @@ def main():
         forms = [args.only] if args.only != "fp64" else []
     form_out = {}
     for name in forms:
-        prec = {"fp32": sse.FP32, "bf16x3": sse.BF16X3}[name]
+        prec = {"fp32": sse.FP32, "bf16x3": sse.BF16X3, "fp64c64": sse.FP64C64}[name]
         ft, _ = time_form(prec, True, True)
         fm = statistics.median(ft)
         tf = prob.flops() / (fm / ncomp) / 1e12
+        if name == "fp64c64":
+            # the binary64 kernel on complex64 inputs and outputs (VALU)
+            roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                    "kernel": "k_sse_fp64<complex64>"}
+        else:
+            roof = {"bound": "mfma", "achieved": round(tf, 3),
+                    "peak": PEAK_MFMA_TFLOPS[name], "unit": "TFLOP/s",
+                    "frac": round(tf / PEAK_MFMA_TFLOPS[name], 4),
+                    "kernel": f"k_sse_mfma<{name}>"}
         form_out[name] = {
             "value": round(prob.flops() * ncomp / fm / 1e9, 1), "unit": "GFLOP/s",
             "ms_per_step": round(fm * 1e3, 3), "ms_per_step_ci95": round(ci95(ft) * 1e3, 3),
             "storage": "complex64", "inputs": "G magnitudes spread over ~8 decades",
-            "roofline": {"bound": "mfma", "achieved": round(tf, 3),
-                         "peak": PEAK_MFMA_TFLOPS[name], "unit": "TFLOP/s",
-                         "frac": round(tf / PEAK_MFMA_TFLOPS[name], 4),
-                         "kernel": f"k_sse_mfma<{name}>"},
-            "speedup_vs_fp64": None}
+            "roofline": roof, "speedup_vs_fp64": None}
         progress(f"form {name}: {fm*1e3:.1f} ms/step")
     if args.only and args.only != "fp64":
         print(json.dumps({"forms": form_out}), flush=True)

@@ -23,7 +23,7 @@
  *   Dt    complex [ncomp][Nqz, Nw, NA, NB, N3D, N3D]
  *   Sigma complex [ncomp][Nkz, NE, NA, Norb, Norb]
  * "complex" is complex128 (16 bytes) for SSE_FP64 and complex64 (8 bytes) for
- * SSE_FP32 and SSE_BF16X3.  With ncomp = 2 the lesser and greater components
+ * SSE_FP32, SSE_BF16X3 and SSE_FP64C64.  With ncomp = 2 the lesser and greater components
  * are stacked on a leading axis; each is computed from its own G and Dt.
  * The workspace is caller-owned device memory of at least the size that
  * sse_plan reports; the library keeps no pointer after the call (or, for
@@ -66,11 +66,18 @@ typedef enum {
 
 typedef enum {
     SSE_FP64 = 0,  /* complex128 storage, binary64 arithmetic throughout */
-    SSE_FP32 = 1,  /* complex64 storage; tap products on fp32 MFMA, fp32 accumulation
-                      within one qz row of taps, binary64 accumulation across rows,
-                      neighbours and in the dH sandwich */
-    SSE_BF16X3 = 2, /* complex64 storage; tap products as bf16 hi*hi + hi*lo + lo*hi on
-                       MFMA with fp32 accumulation within one qz row, binary64 beyond */
+    /* SSE_FP32 and SSE_BF16X3 (complex64 storage, the matrix cores): for each
+       neighbour b the tap sum over (qz, w) runs window by window -- one window
+       is one qz row and one chunk of at most chunk_taps frequencies (all that
+       fit the LDS window when chunk_taps = 0) -- with the tap products and the
+       sum inside a window in fp32 on MFMA, and the window sums added into
+       binary64 accumulators (the sum across qz rows and chunks).  The
+       accumulated sums are then rounded once to fp32 for the dH sandwich,
+       whose Norb x Norb block products run in fp32 on MFMA; the sum over
+       neighbours b is fp32; alpha is applied in binary64 to that fp32 sum and
+       the result is stored as complex64. */
+    SSE_FP32 = 1,   /* tap products in fp32 */
+    SSE_BF16X3 = 2, /* tap products as bf16 hi*hi + hi*lo + lo*hi (x = hi + lo) */
     SSE_FP64C64 = 3 /* complex64 storage, binary64 arithmetic throughout (the fallback
                        of a complex64 job whose sampled check misses its tolerance) */
 } sse_precision;
@@ -88,7 +95,10 @@ typedef struct {
     int32_t prec;  /* sse_precision */
     int32_t tile_e; /* energies per output tile; 0 = the library's default (the largest
                        that fills a workgroup); clamped to [1, that default] */
-    int32_t reserved; /* must be 0 */
+    int32_t chunk_taps; /* at most this many frequencies per tap chunk (one staged G
+                           window); 0 = as many as the window holds.  Under
+                           SSE_FP32/SSE_BF16X3 it bounds the fp32 part of the tap sum;
+                           in every precision it is a tuning parameter.  >= 0 */
     double alpha_re, alpha_im; /* prefactor; Eq. (3) is alpha = i (0 + 1i) */
 } sse_desc;
 

@@ -9,7 +9,8 @@
 
 namespace sse {
 
-TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out)
+TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, int chunk_cap,
+                       TapTable *out)
 {
     const int NN = Norb * Norb;
     int TE = fp64k::kPmax / NN;
@@ -25,7 +26,8 @@ TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     long win_max = 0;
     while (t < taps.n) {
         int u = t + 1;
-        while (u < taps.n && fp64k::kPmax + (long)(taps.s[t] - taps.s[u]) * NN <= budget)
+        while (u < taps.n && (chunk_cap <= 0 || u - t < chunk_cap) &&
+               fp64k::kPmax + (long)(taps.s[t] - taps.s[u]) * NN <= budget)
             ++u;
         out->cb[out->nchunk++] = t;
         win_max = std::max(win_max, fp64k::kPmax + (long)(taps.s[t] - taps.s[u - 1]) * NN);
@@ -50,8 +52,8 @@ void fill_tap_pairs(Fp64Params &p)
     }
 }
 
-TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, TapTable *out,
-                       GroupTable *groups)
+TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, int chunk_cap,
+                       TapTable *out, GroupTable *groups)
 {
     const int NN = Norb * Norb;
     int TE = mfmak::kPwg / NN;
@@ -74,6 +76,7 @@ TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps, int te_request, T
     while (t < taps.n) {
         int u = t + 1;
         while (u < taps.n && u - t < mfmak::kMaxG * mfmak::kGS &&
+               (chunk_cap <= 0 || u - t < chunk_cap) &&
                mfmak::kPwg + (long)(taps.s[t] - taps.s[u]) * NN <= mfmak::kPlaneWords)
             ++u;
         groups->gb[out->nchunk] = groups->n;

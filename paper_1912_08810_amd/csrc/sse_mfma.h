@@ -83,7 +83,7 @@ struct MfmaPrepParams {
 
 // MFMA path (sse_mfma.hip).  prec is SSE_FP32 or SSE_BF16X3.
 TileGeom mfma_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
-                       TapTable *taps_out, GroupTable *groups_out);
+                       int chunk_cap, TapTable *taps_out, GroupTable *groups_out);
 size_t mfma_afrag_bytes(int prec, int NA, int NB, int Nqz, const GroupTable &g);
 // Workspace of one MFMA instance: zero page, A fragments, then (bf16x3) the
 // planar split copy of G at mfma_split_offset.

@@ -124,8 +124,8 @@ sse_status check_desc(const sse_desc *d, const int32_t *w_shift)
         return fail(SSE_ERR_SHAPE, "sse_plan: Nw=%d outside 1..%d", d->Nw, kMaxTaps);
     if (d->ncomp != 1 && d->ncomp != 2)
         return fail(SSE_ERR_SHAPE, "sse_plan: ncomp=%d, must be 1 or 2", d->ncomp);
-    if (d->tile_e < 0 || d->reserved != 0)
-        return fail(SSE_ERR_ARG, "sse_plan: tile_e must be >= 0 and reserved 0");
+    if (d->tile_e < 0 || d->chunk_taps < 0)
+        return fail(SSE_ERR_ARG, "sse_plan: tile_e and chunk_taps must be >= 0");
     for (int w = 0; w < d->Nw; ++w)
         if (w_shift[w] <= -d->NE || w_shift[w] >= d->NE)
             return fail(SSE_ERR_SHAPE, "sse_plan: |w_shift[%d]|=%d not below NE=%d", w, w_shift[w],
@@ -162,13 +162,14 @@ sse_status build_instance(const sse_desc *d, const int32_t *w_shift, Instance *o
     out->d = *d;
     TapTable t = sorted_taps(*d, w_shift);
     if (d->prec == SSE_FP64 || d->prec == SSE_FP64C64) {
-        out->geom = fp64_geometry(d->Norb, d->NE, t, te_request, &out->taps);
+        out->geom = fp64_geometry(d->Norb, d->NE, t, te_request, d->chunk_taps, &out->taps);
     } else {
         if (d->Norb > 22)
             return fail(SSE_ERR_UNSUPPORTED,
                         "sse_plan: the complex64 (MFMA) precisions support Norb <= 22 (got %d)",
                         d->Norb);
-        out->geom = mfma_geometry(d->Norb, d->NE, t, te_request, &out->taps, &out->groups);
+        out->geom = mfma_geometry(d->Norb, d->NE, t, te_request, d->chunk_taps, &out->taps,
+                                  &out->groups);
         out->afrag_bytes = mfma_aux_bytes(d->prec, d->NA, d->NB, d->Nqz, d->Nkz, d->NE, d->Norb,
                                           out->groups);
     }

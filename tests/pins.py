@@ -237,6 +237,71 @@ def pin_generated_inputs(lib=oracle.LIB):
     return e
 
 
+def _sampled_case():
+    """A problem whose block list exercises the sampled evaluation: negative and
+    unsorted shifts, kz wrap (k < Nqz - 1), the output energy edges 0,
+    s_max - 1, s_max and NE - 1, reads of the top G energy (e = 9 with the
+    shift -2), atoms 0 and NA - 1, and repeated, unsorted blocks."""
+    rng = np.random.default_rng(21)
+    p = small_problem(rng, NA=7, NB=3, Norb=3, Nkz=4, Nqz=3, NE=12, shift=(3, -2, 1, 5))
+    smax = int(np.max(p["shift"]))
+    blocks = [(0, 0, 0), (3, 11, 6), (0, smax - 1, 2), (1, smax, 6), (2, 11, 0),
+              (0, 7, 3), (3, 0, 5), (1, 1, 1), (0, 7, 3), (2, 6, 4), (0, 0, 0), (3, smax, 1),
+              (1, 9, 2)]
+    return p, np.array(blocks, dtype=np.int32)
+
+
+def pin_sampled_blocks(lib=oracle.LIB):
+    """The sampled evaluation (a list of output blocks, and G supplied as a
+    stack of only the blocks they read, located through gslot) reproduces the
+    full evaluation bit for bit: each output block of Eq. (3) is a function of
+    its own (k, e, a) and of G blocks that a flat row-major index names."""
+    p, blocks = _sampled_case()
+    Nkz, NE = p["Nkz"], p["NE"]
+    NA, Norb = p["dH"].shape[0], p["dH"].shape[3]
+    Nqz = p["D"].shape[0]
+    full = oracle.sigma(lib=lib, **p)
+    want = full[blocks[:, 0], blocks[:, 1], blocks[:, 2]]
+    # blocks listed, full G
+    got = oracle.sigma(lib=lib, blocks=blocks, **p)
+    assert np.array_equal(got, want)
+    # blocks listed, G as a stack of the needed blocks in a scrambled order
+    need = oracle.needed_g_blocks(p["neigh"], p["shift"], Nkz, Nqz, NE, NA, blocks)
+    order = np.random.default_rng(22).permutation(need.size)
+    Gflat = p["G"].reshape(-1, Norb, Norb)   # row-major: flat index (k NE + e) NA + a
+    stack = Gflat[need[order]]
+    gslot = np.full(Nkz * NE * NA, -1, dtype=np.int64)
+    gslot[need[order]] = np.arange(need.size)
+    got2 = oracle.sigma(lib=lib, blocks=blocks, gslot=gslot, **dict(p, G=stack))
+    assert np.array_equal(got2, want)
+    return 0.0
+
+
+def pin_needed_blocks_exact(lib=oracle.LIB):
+    """needed_g_blocks names exactly the G blocks the listed outputs read:
+    with every listed block supplied the evaluation succeeds and matches the
+    full one (pin_sampled_blocks), and withholding any one of them is reported
+    as a missing block, so no listed block is superfluous."""
+    p, blocks = _sampled_case()
+    Nkz, NE = p["Nkz"], p["NE"]
+    NA, Norb = p["dH"].shape[0], p["dH"].shape[3]
+    Nqz = p["D"].shape[0]
+    need = oracle.needed_g_blocks(p["neigh"], p["shift"], Nkz, Nqz, NE, NA, blocks)
+    assert np.unique(need).size == need.size
+    Gflat = p["G"].reshape(-1, Norb, Norb)
+    for drop in range(need.size):
+        keep = np.delete(need, drop)
+        gslot = np.full(Nkz * NE * NA, -1, dtype=np.int64)
+        gslot[keep] = np.arange(keep.size)
+        try:
+            oracle.sigma(lib=lib, blocks=blocks, gslot=gslot, **dict(p, G=Gflat[keep]))
+        except ValueError:
+            continue
+        raise AssertionError(f"block {need[drop]} withheld but not reported missing")
+    return 0.0
+
+
 ALL_PINS = [pin_single_term, pin_fft_correlation, pin_closed_form_constant, pin_antihermitian,
             pin_kz_roll, pin_energy_shift_and_edge, pin_atom_relabel, pin_linearity,
-            pin_hand_example, pin_generated_inputs]
+            pin_hand_example, pin_generated_inputs, pin_sampled_blocks,
+            pin_needed_blocks_exact]

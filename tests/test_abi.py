@@ -102,11 +102,13 @@ def test_batch_plan_validation():
         sse.sse_plan_batch(many, [np.arange(1, 5)] * 65)
 
 
-def test_tile_e_and_reserved_fields():
+def test_tile_e_and_chunk_taps_fields():
     sse = _sse()
     assert plan_status(tile_e=3)[0] == 0
     assert plan_status(tile_e=-1)[0] == sse.ERR_ARG
+    assert plan_status(chunk_taps=2)[0] == 0
+    assert plan_status(chunk_taps=3, prec=2)[0] == 0
     d = sse.make_desc(16, 4, 4, 3, 3, 64, 4)
-    d.reserved = 1
+    d.chunk_taps = -1
     with pytest.raises(sse.SSEError):
         sse.sse_plan(d, np.arange(1, 5))

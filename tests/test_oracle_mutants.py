@@ -32,6 +32,14 @@ MUTANTS = {
     # dH of the neighbour atom instead of the bond (a, b)
     "dh_of_f": ("const double *Ai = dH + (((size_t)a * d->NB + b) * N3 + i) * nn;",
                 "const double *Ai = dH + (((size_t)(f % d->NA) * d->NB + b) * N3 + i) * nn;"),
+    # sampled evaluation: (k, e) of a listed block swapped
+    "blk_k_e_swapped": ("k = blk[3 * t];\n            e = blk[3 * t + 1];",
+                        "k = blk[3 * t + 1];\n            e = blk[3 * t];"),
+    # sampled evaluation: G block looked up with energy and momentum exchanged
+    "gslot_index": ("const int64_t s = gslot[bidx];",
+                    "const int64_t s = gslot[((int64_t)ee * d->Nkz + kk) * d->NA + f];"),
+    # sampled evaluation: output slot of a listed block off by one
+    "blk_out_slot": ("out + (size_t)t * nn2);", "out + (size_t)((t + 1) % nblk) * nn2);"),
     # out-of-range energies wrapped instead of zero-padded
     "energy_wrap": ("if (ee < 0 || ee >= d->NE)\n                    continue;",
                     "if (ee < 0 || ee >= d->NE)\n                    ee_wrap_marker;"),
@@ -60,6 +68,39 @@ def test_mutant_is_caught(name, tmp_path):
     for pin in pins.ALL_PINS:
         try:
             pin(lib=lib)
+        except (AssertionError, ValueError):
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"
+
+
+# Mistakes in the bookkeeping of the sampled evaluation (oracle/__init__.py).
+PY_MUTANTS = {
+    "needed_kz_sign": ("kk = (k - q) % Nkz", "kk = (k + q) % Nkz"),
+    "needed_energy_sign": ("ee = e - s", "ee = e + s"),
+    "needed_atom_a": ("* NA + int(f))", "* NA + int(a))"),
+    "needed_drops_top_edge": ("0 <= ee < NE", "0 <= ee < NE - 1"),
+    # the atom's own G blocks listed as well as its neighbours'
+    "needed_extra_self": ("need.add((kk * NE + ee) * NA + int(f))",
+                          "need.add((kk * NE + ee) * NA + int(f)); "
+                          "need.add((kk * NE + ee) * NA + int(a))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_needed_blocks_mutant_is_caught(name, monkeypatch):
+    import inspect
+    import textwrap
+    import numpy as np
+    old, new = PY_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(oracle.needed_g_blocks))
+    assert src.count(old) == 1, f"pattern for {name} not found"
+    ns = {"np": np}
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(oracle, "needed_g_blocks", ns["needed_g_blocks"])
+    caught = []
+    for pin in (pins.pin_sampled_blocks, pins.pin_needed_blocks_exact):
+        try:
+            pin()
         except (AssertionError, ValueError):
             caught.append(pin.__name__)
     assert caught, f"mutant {name} passed every pin"

@@ -147,6 +147,29 @@ sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, 
                        const void *Dt, void *Sigma, void *workspace, size_t workspace_bytes,
                        void *stream);
 
+/* Size of the device scratch that sse_compute_noalloc uses: 32 MiB, one copy per
+ * GPU the library runs on, held until the process ends. */
+#define SSE_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * sse_compute without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, result and statuses as
+ * sse_compute, and the same kernels; the scratch those kernels need (the
+ * status word and, for SSE_FP32/SSE_BF16X3, the MFMA fragments and the split
+ * of G) lives in a static device array of SSE_NOALLOC_SCRATCH_BYTES on the
+ * current device, whose address is looked up the first time the current device
+ * calls this function.  The call allocates nothing (no hipMalloc, no pinned
+ * host memory, no events): it enqueues the work on `stream`, which must belong
+ * to the current device, copies the status word back and synchronizes the
+ * stream.  SSE_ERR_UNSUPPORTED if the plan needs more scratch than the array
+ * holds (then use sse_compute), SSE_ERR_ARG for a batch plan or a NULL pointer.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (from several threads or streams) race and must not be made.
+ */
+sse_status sse_compute_noalloc(sse_plan_t plan, const int32_t *neigh, const double *dH,
+                               const void *G, const void *Dt, void *Sigma, void *stream);
+
 /*
  * Enqueue the computation for every instance of the plan (args has one entry
  * per instance) on `stream` and return at once with a ticket.

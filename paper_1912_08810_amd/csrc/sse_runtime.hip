@@ -19,6 +19,13 @@
 
 using namespace sse;
 
+// Device scratch of sse_compute_noalloc: the status word and, for the complex64
+// precisions, the MFMA auxiliary data that sse_compute takes from the caller's
+// workspace.  One copy per GPU, held for the life of the process.  In host code
+// the name stands for a host-side shadow, never a device address: kernels get
+// the address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SSE_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -705,6 +712,18 @@ sse_status sse_submit(sse_plan_t plan, const sse_args *args, void *workspace,
     return ticket_finish_enqueue(tk, dstatus, sizeof(uint32_t), s, ticket);
 }
 
+// Status of a finished submission from its device status word.
+static sse_status status_from_word(uint32_t hs)
+{
+    if (hs & kStatusBadNeigh)
+        return fail(SSE_ERR_NEIGH, "a neighbour index is outside [0, NA)");
+    if (hs & kStatusBadBlock)
+        return fail(SSE_ERR_ARG, "sse_check_submit: a listed block is outside the output");
+    if (hs != 0)
+        return fail(SSE_ERR_DEVICE, "device status word 0x%x", hs);
+    return SSE_OK;
+}
+
 static sse_status finish_ticket(uint64_t ticket, bool block)
 {
     Ticket tk;
@@ -736,12 +755,9 @@ static sse_status finish_ticket(uint64_t ticket, bool block)
     ticket_release(tk);
     if (e != hipSuccess)
         return hip_fail(e, "waiting for a submission");
-    if (hs & kStatusBadNeigh)
-        return fail(SSE_ERR_NEIGH, "a neighbour index is outside [0, NA)");
-    if (hs & kStatusBadBlock)
-        return fail(SSE_ERR_ARG, "sse_check_submit: a listed block is outside the output");
-    if (hs != 0)
-        return fail(SSE_ERR_DEVICE, "device status word 0x%x", hs);
+    const sse_status hst = status_from_word(hs);
+    if (hst != SSE_OK)
+        return hst;
     if (tk.ncheck > 0) {
         bool miss = false;
         for (int c = 0; c < tk.ncheck; ++c) {
@@ -759,6 +775,79 @@ static sse_status finish_ticket(uint64_t ticket, bool block)
 sse_status sse_poll(uint64_t ticket) { return finish_ticket(ticket, false); }
 
 sse_status sse_wait(uint64_t ticket) { return finish_ticket(ticket, true); }
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+sse_status scratch_for_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_compute_noalloc: device %d above %d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(SSE_ERR_DEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sse_status sse_compute_noalloc(sse_plan_t plan, const int32_t *neigh, const double *dH,
+                               const void *G, const void *Dt, void *Sigma, void *stream)
+{
+    if (!plan)
+        return fail(SSE_ERR_ARG, "sse_compute_noalloc: NULL plan");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_compute_noalloc: needs a single-instance plan");
+    if (!neigh || !dH || !G || !Dt || !Sigma)
+        return fail(SSE_ERR_ARG, "sse_compute_noalloc: NULL tensor pointer");
+    if (plan->ws_bytes > (size_t)SSE_NOALLOC_SCRATCH_BYTES)
+        return fail(SSE_ERR_UNSUPPORTED,
+                    "sse_compute_noalloc: the plan needs %zu bytes of scratch, the static scratch "
+                    "holds %zu (use sse_compute with a workspace)",
+                    plan->ws_bytes, (size_t)SSE_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    sse_status st = scratch_for_current_device(&ws);
+    if (st != SSE_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *dstatus = (uint32_t *)ws;
+    hipError_t e = launch_clear_status(dstatus, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "clear_status launch");
+    sse_args a{neigh, dH, G, Dt, Sigma};
+    st = enqueue_instance(plan->inst[0], a, dstatus, (char *)ws + kStatusBytes, s);
+    if (st != SSE_OK)
+        return st;
+    uint32_t hs = 0xffffffffu;
+    e = hipMemcpyAsync(&hs, dstatus, sizeof hs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "sse_compute_noalloc: waiting for the computation");
+    return status_from_word(hs);
+}
 
 sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
                        const void *Dt, void *Sigma, void *workspace, size_t workspace_bytes,

@@ -68,6 +68,7 @@ def _load():
     L.sse_plan_batch.argtypes = [c.POINTER(sse_desc), c.POINTER(vp), c.c_int32, c.POINTER(vp),
                                  c.POINTER(c.c_size_t)]
     L.sse_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
+    L.sse_compute_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
                              c.POINTER(c.c_uint64)]
     L.sse_check_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_int32, c.c_double, vp, vp,
@@ -77,8 +78,8 @@ def _load():
     L.sse_plan_destroy.argtypes = [vp]
     L.sse_plan_destroy.restype = None
     L.sse_last_error.restype = c.c_char_p
-    for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_submit, L.sse_poll, L.sse_wait,
-              L.sse_check_submit):
+    for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_compute_noalloc, L.sse_submit,
+              L.sse_poll, L.sse_wait, L.sse_check_submit):
         f.restype = c.c_int
     return L
 
@@ -86,8 +87,9 @@ def _load():
 lib = _load()
 
 # Every symbol include/sse.h declares (checked by the CPU test of the library).
-EXPORTS = ["sse_check_submit", "sse_compute", "sse_last_error", "sse_plan", "sse_plan_batch",
-           "sse_plan_destroy", "sse_poll", "sse_submit", "sse_wait"]
+EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_last_error", "sse_plan",
+           "sse_plan_batch", "sse_plan_destroy", "sse_poll", "sse_submit", "sse_wait"]
+NOALLOC_SCRATCH_BYTES = 32 << 20  # SSE_NOALLOC_SCRATCH_BYTES
 
 
 def last_error() -> str:
@@ -151,7 +153,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.sse_plan_destroy(h)
             self.handle = None
 
@@ -168,6 +170,13 @@ def sse_compute(plan: Plan, neigh, dH, G, Dt, Sigma, workspace, stream=None, che
     st = lib.sse_compute(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt), _ptr(Sigma),
                          _ptr(workspace), plan.workspace_bytes, _stream(stream))
     return _check(st, "sse_compute") if check else st
+
+
+def sse_compute_noalloc(plan: Plan, neigh, dH, G, Dt, Sigma, stream=None, check=True) -> int:
+    """sse_compute with the library's static device scratch instead of a workspace."""
+    st = lib.sse_compute_noalloc(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt),
+                                 _ptr(Sigma), _stream(stream))
+    return _check(st, "sse_compute_noalloc") if check else st
 
 
 def _args(items):

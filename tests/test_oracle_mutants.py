@@ -104,3 +104,96 @@ def test_needed_blocks_mutant_is_caught(name, monkeypatch):
         except (AssertionError, ValueError):
             caught.append(pin.__name__)
     assert caught, f"mutant {name} passed every pin"
+
+
+# Plausible mistakes in the phonon self-energy oracle (oracle/pi_oracle.c).
+PI_MUTANTS = {
+    # dH_ba read as dH_ab instead of its transpose
+    "pi_no_transpose": ("sr += Ai[l * No + m] * x[2 * (l * No + n)];\n"
+                        "                                si += Ai[l * No + m] * x[2 * (l * No + n) + 1];",
+                        "sr += Ai[m * No + l] * x[2 * (l * No + n)];\n"
+                        "                                si += Ai[m * No + l] * x[2 * (l * No + n) + 1];"),
+    # kz - qz instead of kz + qz
+    "pi_kz_sign": ("const int kk = (k + q) % d->Nkz;", "const int kk = (k - q + d->Nkz) % d->Nkz;"),
+    # E - omega instead of E + omega
+    "pi_energy_sign": ("const int ee = e + shift[w];", "const int ee = e - shift[w];"),
+    # Y transposed inside the trace
+    "pi_y_transposed": ("const double br = y[2 * (l * No + m)], bi = y[2 * (l * No + m) + 1];",
+                        "const double br = y[2 * (m * No + l)], bi = y[2 * (m * No + l) + 1];"),
+    # the shifted Green's function taken from the neighbour, the other from the atom
+    "pi_roles_swapped": ("kk, ee, a, &missing);", "kk, ee, f, &missing);"),
+    # diagonal block with the sign of the neighbour blocks
+    "pi_diag_sign": ("out[2 * ((size_t)NB * N3 * N3 + x)] = -(beta_re * r - beta_im * im);",
+                     "out[2 * ((size_t)NB * N3 * N3 + x)] = (beta_re * r - beta_im * im);"),
+    # last neighbour left out of the diagonal
+    "pi_diag_drops_b": ("for (int b = 0; b < NB; ++b) {\n            r += ",
+                        "for (int b = 0; b < NB - 1; ++b) {\n            r += "),
+    # last kz point dropped
+    "pi_dropped_k": ("for (int k = 0; k < d->Nkz; ++k) {", "for (int k = 0; k < d->Nkz - 1; ++k) {"),
+    # conjugated prefactor
+    "pi_beta_conj": ("out[2 * ((size_t)b * N3 * N3 + x) + 1] = beta_re * im + beta_im * r;",
+                     "out[2 * ((size_t)b * N3 * N3 + x) + 1] = beta_re * im - beta_im * r;"),
+    # (i, j) of the output exchanged
+    "pi_ij_swapped": ("Pb[2 * (i * N3 + j)] += tr;\n                        Pb[2 * (i * N3 + j) + 1] += ti;",
+                      "Pb[2 * (j * N3 + i)] += tr;\n                        Pb[2 * (j * N3 + i) + 1] += ti;"),
+    # sign error in the complex trace
+    "pi_complex_sign": ("ti += ar * bi + ai * br;", "ti += ar * bi - ai * br;"),
+    # sampled evaluation: (q, w) of a listed block swapped
+    "pi_blk_q_w_swapped": ("q = blk[3 * t];\n            w = blk[3 * t + 1];",
+                           "q = blk[3 * t + 1] % Nqz;\n            w = blk[3 * t] % Nw;"),
+    # sampled evaluation: slot looked up with energy and momentum exchanged
+    "pi_gslot_index": ("if (gslot[flat] < 0) {", "if (gslot[flat] < 0 || (flat = ((int64_t)e * d->Nkz + k) * d->NA + atom, 0)) {"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PI_MUTANTS))
+def test_pi_mutant_is_caught(name, tmp_path):
+    from tests import pins_pi
+    old, new = PI_MUTANTS[name]
+    src = open(oracle.PI_SRC).read()
+    assert src.count(old) >= 1, f"pattern for {name} not found"
+    mutated = src.replace(old, new)
+    if name == "pi_gslot_index":
+        mutated = mutated.replace("const int64_t flat = ((int64_t)k * d->NE + e) * d->NA + atom;",
+                                  "int64_t flat = ((int64_t)k * d->NE + e) * d->NA + atom;")
+    path = os.path.join(tmp_path, f"m_{name}.c")
+    with open(path, "w") as fh:
+        fh.write(mutated)
+    lib = oracle.build(src=path, out=os.path.join(tmp_path, f"libm_{name}.so"))
+    caught = []
+    for pin in pins_pi.PI_PINS:
+        try:
+            pin(lib=lib)
+        except (AssertionError, ValueError):
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"
+
+
+# Mistakes in the D~ combination and the retarded relation (oracle/__init__.py).
+DT_MUTANTS = {
+    "dt_no_reverse_map": ("D[:, :, f, r] - D[:, :, f, NB]", "D[:, :, a, b] - D[:, :, f, NB]"),
+    "dt_diag_of_a_for_b": ("- D[:, :, f, NB] - D[:, :, a, NB]", "- D[:, :, a, NB] - D[:, :, a, NB]"),
+    "dt_sign": ("- D[:, :, a, NB] + D[:, :, a, b]", "+ D[:, :, a, NB] + D[:, :, a, b]"),
+    "dt_reverse_slot": ("r = slots[0]", "r = (slots[0] + 1) % NB"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DT_MUTANTS))
+def test_dtilde_mutant_is_caught(name, monkeypatch):
+    import inspect
+    import textwrap
+    import numpy as np
+    from tests import pins_pi
+    old, new = DT_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(oracle.dtilde))
+    assert src.count(old) == 1, f"pattern for {name} not found"
+    ns = {"np": np}
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(oracle, "dtilde", ns["dtilde"])
+    caught = []
+    for pin in (pins_pi.pin_dtilde_structure, pins_pi.pin_dtilde_sigma_antihermitian):
+        try:
+            pin()
+        except (AssertionError, ValueError):
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"

@@ -61,6 +61,23 @@ int main() {
     if (sse_submit(p2, &a, W.data(), ws, nullptr, &tb2)) { printf("submit after a pending poll: %s\n", sse_last_error()); return 4; }
     sse_wait(ta); sse_wait(tb2);
   }
+  {
+    // allocation-free variant: the plan's scratch comes from the static array
+    sse_desc n1 = d; n1.prec = SSE_FP64; n1.ncomp = 2;
+    sse_plan_t pn; size_t wsn;
+    if (sse_plan(&n1, sh, &pn, &wsn)) return 6;
+    for (int it = 0; it < 3; ++it)
+      if (sse_compute_noalloc(pn, neigh.data(), dH.data(), G.data(), D.data(), S.data(), nullptr)) {
+        printf("noalloc: %s\n", sse_last_error()); return 7; }
+    if (sse_compute_noalloc(pn, nullptr, dH.data(), G.data(), D.data(), S.data(), nullptr) != SSE_ERR_ARG) return 8;
+    sse_plan_destroy(pn);
+    sse_desc big = d; big.prec = SSE_BF16X3; big.NA = 1024; big.NE = 1000; big.Nkz = 7; big.Nqz = 7;
+    sse_plan_t pbig; size_t wsbig;
+    if (sse_plan(&big, sh, &pbig, &wsbig)) return 9;
+    if (wsbig <= SSE_NOALLOC_SCRATCH_BYTES) return 10;
+    if (sse_compute_noalloc(pbig, neigh.data(), dH.data(), G.data(), D.data(), S.data(), nullptr) != SSE_ERR_UNSUPPORTED) return 11;
+    sse_plan_destroy(pbig);
+  }
   printf("OK\n");
   return 0;
 }

@@ -13,6 +13,8 @@
 #define __global__
 #define __forceinline__ inline
 #define __host__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 struct float2 { float x, y; };
 struct double2 { double x, y; };
 struct uint2 { unsigned x, y; };
@@ -38,5 +40,7 @@ inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->recorded = 1; e
 inline hipError_t hipEventQuery(hipEvent_t e) { if (e->polls++ < 2) { g_fake_last = hipErrorNotReady; return hipErrorNotReady; } return hipSuccess; }
 inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = const_cast<void *>(sym); return hipSuccess; }
 inline hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
 template <class T> T atomicAdd(T *p, T v) { T o = *p; *p += v; return o; }

@@ -195,6 +195,36 @@ sse_status sse_check_submit(sse_plan_t plan, const sse_args *args, const int32_t
                             int32_t nblocks, double tol, double *rel_err, void *workspace,
                             size_t workspace_bytes, void *stream, uint64_t *ticket);
 
+/*
+ * Phonon scattering self-energy, Eqs. (4) and (5) (Sec. 2), for a
+ * single-instance SSE_FP64 plan (the same desc: sizes, shift table, ncomp;
+ * alpha is the prefactor beta of Eq. (5), i in the paper).  For frequency w,
+ * momentum q, atom a and neighbour slot b < NB (f = neigh[a, b]):
+ *
+ *   P_ij[q, w, a, b] = sum_k sum_e tr( dH[a, b, i]^T . X[(k + q) mod Nkz, e + s_w, a]
+ *                                     . dH[a, b, j] . Y[k, e, f] )
+ *   Pi[q, w, a, b,  i, j] =  alpha * P_ij[q, w, a, b]          (Eq. (5))
+ *   Pi[q, w, a, NB, i, j] = -sum_b Pi[q, w, a, b, i, j]       (Eq. (4), the diagonal)
+ *
+ * where terms with e + s_w outside [0, NE) are zero, dH[a, b, i]^T stands for
+ * the back-bond derivative (real H), and X, Y are opposite components: the
+ * lesser Pi takes X = G<, Y = G>, the greater one X = G>, Y = G<.  G always
+ * holds both components, complex128 [2][Nkz, NE, NA, Norb, Norb] (lesser
+ * first); Pi is complex128 [ncomp][Nqz, Nw, NA, NB + 1, 3, 3] (ncomp = 1: the
+ * lesser only), overwritten, in the layout of the phonon Green's function
+ * (Sec. 2) with the diagonal block in slot NB.  Workspace: at least 256 bytes.
+ * SSE_ERR_UNSUPPORTED for another precision or Norb > 16; SSE_ERR_NEIGH (at
+ * poll) for a neighbour index outside [0, NA), whose block is left zero.
+ * Returns at once with a ticket (sse_poll / sse_wait).
+ */
+sse_status sse_pi_submit(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
+                         void *Pi, void *workspace, size_t workspace_bytes, void *stream,
+                         uint64_t *ticket);
+
+/* sse_pi_submit, then wait for it. */
+sse_status sse_pi_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
+                          void *Pi, void *workspace, size_t workspace_bytes, void *stream);
+
 /* SSE_PENDING while the submission runs, else its final status (the ticket is
  * then released; polling it again gives SSE_ERR_ARG). */
 sse_status sse_poll(uint64_t ticket);

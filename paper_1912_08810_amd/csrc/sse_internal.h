@@ -185,6 +185,51 @@ struct Fp64Params {
 void fill_tap_pairs(Fp64Params &p);
 
 
+// Phonon self-energy kernel (sse_pi.hip): 256 threads, each holding the 9 (i, j)
+// accumulators of kNT taps; up to kMaxGroups tap groups per workgroup.
+namespace pik {
+constexpr int kBlock = 256;
+constexpr int kNT = 4;
+constexpr int kMaxGroups = 8;
+constexpr size_t kLdsBudget = 78 * 1024;     // two workgroups per CU
+constexpr size_t kLdsBudgetOne = 156 * 1024; // one workgroup per CU (large Norb)
+constexpr int kMaxNorb = 16;                 // a G block row fits one load per thread
+}  // namespace pik
+
+// Tap chunks of the phonon kernel: taps sorted by increasing shift (tap t uses
+// frequency tw[t], shift ts[t]); chunk c covers taps [cb[c], cb[c+1]) with
+// cg[c] tap groups (a power of two) and a ring of at most R rows.
+struct PiGeom {
+    int32_t nchunk;
+    int32_t R;
+    int32_t cb[kMaxTaps + 1];
+    int32_t cg[kMaxTaps];
+    int32_t tw[kMaxTaps];
+    int32_t ts[kMaxTaps];
+    size_t lds_bytes;
+    size_t lds_budget;
+    bool ok;
+};
+
+struct PiParams {
+    const double2 *X;  // the component whose energy is shifted (Pi<: G<)
+    const double2 *Y;  // the opposite component (Pi<: G>)
+    const double *dH;
+    const int32_t *neigh;
+    double2 *Pi;       // [Nqz, Nw, NA, NB + 1, 3, 3]
+    int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
+    int32_t nchunk, R;
+    int32_t cb[kMaxTaps + 1];
+    int32_t cg[kMaxTaps];
+    int32_t tw[kMaxTaps];
+    int32_t ts[kMaxTaps];
+    int64_t n_wg;      // NA * NB * Nqz * nchunk
+    double beta_re, beta_im;
+};
+
+PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw);
+hipError_t pi_launch(const PiParams &p, size_t lds_bytes, hipStream_t s);
+
 // Sampled binary64 check of a complex64 result (sse_check.hip).
 struct CheckParams {
     const int32_t *neigh;

@@ -53,6 +53,7 @@ struct Instance {
     GroupTable groups;  // MFMA path: tap groups per chunk
     TileGeom geom;
     size_t afrag_bytes = 0;  // MFMA path: workspace for the A fragments (+ split G, bf16x3)
+    int32_t shift[kMaxTaps] = {};  // the caller's shift table, in frequency order
 };
 
 constexpr size_t kStatusBytes = 256;  // status word region at the start of the workspace
@@ -167,6 +168,8 @@ sse_status build_instance(const sse_desc *d, const int32_t *w_shift, Instance *o
     if (st != SSE_OK)
         return st;
     out->d = *d;
+    for (int w = 0; w < d->Nw; ++w)
+        out->shift[w] = w_shift[w];
     TapTable t = sorted_taps(*d, w_shift);
     if (d->prec == SSE_FP64 || d->prec == SSE_FP64C64) {
         out->geom = fp64_geometry(d->Norb, d->NE, t, te_request, d->chunk_taps, &out->taps);
@@ -847,6 +850,86 @@ sse_status sse_compute_noalloc(sse_plan_t plan, const int32_t *neigh, const doub
     if (e != hipSuccess)
         return hip_fail(e, "sse_compute_noalloc: waiting for the computation");
     return status_from_word(hs);
+}
+
+sse_status sse_pi_submit(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
+                         void *Pi, void *workspace, size_t workspace_bytes, void *stream,
+                         uint64_t *ticket)
+{
+    if (!plan || !ticket || !neigh || !dH || !G || !Pi)
+        return fail(SSE_ERR_ARG, "sse_pi_submit: NULL argument");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_pi_submit: needs a single-instance plan");
+    const Instance &I = plan->inst[0];
+    const sse_desc &d = I.d;
+    if (d.prec != SSE_FP64)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_pi_submit: the phonon self-energy is SSE_FP64 only");
+    if (d.Norb > pik::kMaxNorb)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_pi_submit: Norb <= %d (got %d)", pik::kMaxNorb,
+                    d.Norb);
+    if (!workspace || workspace_bytes < kStatusBytes)
+        return fail(SSE_ERR_ARG, "sse_pi_submit: workspace of %zu bytes needed", kStatusBytes);
+    const PiGeom gm = pi_geometry(d.Norb, I.shift, d.Nw);
+    if (!gm.ok)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_pi_submit: Norb=%d leaves no room for the ring",
+                    d.Norb);
+    const int64_t n_wg = (int64_t)d.NA * d.NB * d.Nqz * gm.nchunk;
+    if (n_wg > 0x7fffffffLL)
+        return fail(SSE_ERR_SHAPE, "sse_pi_submit: %lld workgroups exceed one launch",
+                    (long long)n_wg);
+    hipStream_t s = (hipStream_t)stream;
+    Ticket tk;
+    sse_status st = ticket_acquire(&tk);
+    if (st != SSE_OK)
+        return st;
+    uint32_t *dstatus = (uint32_t *)workspace;
+    hipError_t e = launch_clear_status(dstatus, s);
+    if (e == hipSuccess)
+        e = launch_validate_neigh(neigh, (int64_t)d.NA * d.NB, d.NA, dstatus, s);
+    const size_t NN = (size_t)d.Norb * d.Norb;
+    const size_t g_elems = (size_t)d.Nkz * d.NE * d.NA * NN;
+    const size_t pi_elems = (size_t)d.Nqz * d.Nw * d.NA * (d.NB + 1) * kNF;
+    for (int c = 0; c < d.ncomp && e == hipSuccess; ++c) {
+        PiParams pp{};
+        pp.X = (const double2 *)G + (size_t)c * g_elems;
+        pp.Y = (const double2 *)G + (size_t)(1 - c) * g_elems;
+        pp.dH = dH;
+        pp.neigh = neigh;
+        pp.Pi = (double2 *)Pi + (size_t)c * pi_elems;
+        pp.NA = d.NA;
+        pp.NB = d.NB;
+        pp.Norb = d.Norb;
+        pp.NN = (int)NN;
+        pp.Nkz = d.Nkz;
+        pp.Nqz = d.Nqz;
+        pp.NE = d.NE;
+        pp.Nw = d.Nw;
+        pp.nchunk = gm.nchunk;
+        pp.R = gm.R;
+        memcpy(pp.cb, gm.cb, sizeof pp.cb);
+        memcpy(pp.cg, gm.cg, sizeof pp.cg);
+        memcpy(pp.tw, gm.tw, sizeof pp.tw);
+        memcpy(pp.ts, gm.ts, sizeof pp.ts);
+        pp.n_wg = n_wg;
+        pp.beta_re = d.alpha_re;
+        pp.beta_im = d.alpha_im;
+        e = pi_launch(pp, gm.lds_bytes, s);
+    }
+    if (e != hipSuccess) {
+        ticket_release(tk);
+        return hip_fail(e, "phonon kernel launch");
+    }
+    return ticket_finish_enqueue(tk, dstatus, sizeof(uint32_t), s, ticket);
+}
+
+sse_status sse_pi_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
+                          void *Pi, void *workspace, size_t workspace_bytes, void *stream)
+{
+    uint64_t t = 0;
+    sse_status st = sse_pi_submit(plan, neigh, dH, G, Pi, workspace, workspace_bytes, stream, &t);
+    if (st != SSE_OK)
+        return st;
+    return sse_wait(t);
 }
 
 sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,

@@ -69,6 +69,8 @@ def _load():
                                  c.POINTER(c.c_size_t)]
     L.sse_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
     L.sse_compute_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.sse_pi_submit.argtypes = [vp, vp, vp, vp, vp, vp, c.c_size_t, vp, c.POINTER(c.c_uint64)]
+    L.sse_pi_compute.argtypes = [vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
     L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
                              c.POINTER(c.c_uint64)]
     L.sse_check_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_int32, c.c_double, vp, vp,
@@ -79,7 +81,7 @@ def _load():
     L.sse_plan_destroy.restype = None
     L.sse_last_error.restype = c.c_char_p
     for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_compute_noalloc, L.sse_submit,
-              L.sse_poll, L.sse_wait, L.sse_check_submit):
+              L.sse_poll, L.sse_wait, L.sse_check_submit, L.sse_pi_submit, L.sse_pi_compute):
         f.restype = c.c_int
     return L
 
@@ -87,8 +89,9 @@ def _load():
 lib = _load()
 
 # Every symbol include/sse.h declares (checked by the CPU test of the library).
-EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_last_error", "sse_plan",
-           "sse_plan_batch", "sse_plan_destroy", "sse_poll", "sse_submit", "sse_wait"]
+EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_last_error",
+           "sse_pi_compute", "sse_pi_submit", "sse_plan", "sse_plan_batch", "sse_plan_destroy",
+           "sse_poll", "sse_submit", "sse_wait"]
 NOALLOC_SCRATCH_BYTES = 32 << 20  # SSE_NOALLOC_SCRATCH_BYTES
 
 
@@ -177,6 +180,30 @@ def sse_compute_noalloc(plan: Plan, neigh, dH, G, Dt, Sigma, stream=None, check=
     st = lib.sse_compute_noalloc(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt),
                                  _ptr(Sigma), _stream(stream))
     return _check(st, "sse_compute_noalloc") if check else st
+
+
+def pi_elems(desc) -> int:
+    """Complex elements of one component of Pi: [Nqz, Nw, NA, NB + 1, 3, 3]."""
+    return desc.Nqz * desc.Nw * desc.NA * (desc.NB + 1) * 9
+
+
+def sse_pi_compute(plan: Plan, neigh, dH, G, Pi, workspace, stream=None, check=True) -> int:
+    """Phonon self-energy (Eqs. (4)-(5)); G holds both components, Pi ncomp."""
+    nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") \
+        else plan.workspace_bytes
+    st = lib.sse_pi_compute(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Pi),
+                            _ptr(workspace), nbytes, _stream(stream))
+    return _check(st, "sse_pi_compute") if check else st
+
+
+def sse_pi_submit(plan: Plan, neigh, dH, G, Pi, workspace, stream=None) -> int:
+    t = ctypes.c_uint64()
+    nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") \
+        else plan.workspace_bytes
+    _check(lib.sse_pi_submit(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Pi),
+                             _ptr(workspace), nbytes, _stream(stream), ctypes.byref(t)),
+           "sse_pi_submit")
+    return t.value
 
 
 def _args(items):

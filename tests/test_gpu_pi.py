@@ -1,0 +1,108 @@
+"""Parity of the binary64 phonon self-energy kernel (Eqs. (4)-(5)) with the
+oracle, through the C ABI.
+
+Tolerance: relative Frobenius error <= 1e-12 per component (the binary64
+bar), and element-wise deviation <= 1e-12 of the largest |Pi| element.  Cases
+span the CPU-scale configuration, ragged and odd shapes (Norb 1..16, negative
+and unsorted shifts, more taps than one workgroup holds, Nqz < Nkz, a single
+energy), self and duplicate neighbours, a general prefactor, the
+device-scale configuration on sampled blocks, and the error paths.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_08810_amd import configs
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def check_full(dp, Pi, ncomp=2, beta=1j):
+    for c in range(ncomp):
+        got = gu.pi_host(Pi, c, dp.prob)
+        want = gu.oracle_pi_full(dp, c, beta=beta)
+        e1, e2 = gu.rel_fro(got, want), gu.max_elem_rel(got, want)
+        print(f"  comp {c}: rel_fro={e1:.3e} max_elem={e2:.3e}", flush=True)
+        assert e1 <= TOL and e2 <= TOL, (c, e1, e2)
+
+
+def test_small_config_full_both_components():
+    dp = gu.DeviceProblem(configs.SMALL, configs.SEED, ncomp=2)
+    st, Pi = gu.run_pi(dp)
+    assert st == 0
+    check_full(dp, Pi)
+    # lesser Pi keeps the anti-Hermitian symmetry of its inputs, block by block
+    x = gu.pi_host(Pi, 0, dp.prob)
+    assert np.linalg.norm(x + np.conj(np.swapaxes(x, -1, -2))) <= 1e-13 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("prob", [
+    configs.Problem(NA=7, NB=3, Norb=5, Nkz=4, Nqz=3, NE=23, Nw=6, shift=(3, -2, 1, 5, 0, 7)),
+    configs.Problem(NA=3, NB=1, Norb=1, Nkz=1, Nqz=1, NE=5, Nw=1),
+    configs.Problem(NA=5, NB=2, Norb=16, Nkz=2, Nqz=2, NE=9, Nw=3, shift=(2, -1, 4)),
+    configs.Problem(NA=6, NB=2, Norb=3, Nkz=3, Nqz=2, NE=30, Nw=40, shift=tuple(range(-20, 20))),
+    configs.Problem(NA=9, NB=4, Norb=10, Nkz=3, Nqz=3, NE=37, Nw=30),
+    configs.Problem(NA=4, NB=3, Norb=7, Nkz=5, Nqz=5, NE=1, Nw=2, shift=(0, 0)),
+], ids=["odd", "norb1", "norb16", "two_chunks", "norb10_nw30", "one_energy"])
+def test_shapes(prob):
+    dp = gu.DeviceProblem(prob, 17, ncomp=2)
+    st, Pi = gu.run_pi(dp)
+    assert st == 0
+    check_full(dp, Pi)
+
+
+def test_self_and_duplicate_neighbours_and_general_prefactor():
+    prob = configs.Problem(NA=6, NB=4, Norb=4, Nkz=3, Nqz=2, NE=17, Nw=5)
+    rng = np.random.default_rng(5)
+    neigh = rng.integers(0, prob.NA, size=(prob.NA, prob.NB)).astype(np.int32)
+    neigh[:, 0] = np.arange(prob.NA)           # every atom its own neighbour
+    neigh[:, 2] = neigh[:, 1]                  # a duplicate entry in every row
+    dp = gu.DeviceProblem(prob, 23, ncomp=2, neigh=neigh)
+    beta = 0.3 - 0.7j
+    st, Pi = gu.run_pi(dp, beta=beta)
+    assert st == 0
+    check_full(dp, Pi, beta=beta)
+
+
+def test_lesser_only():
+    dp = gu.DeviceProblem(configs.SMALL, 3, ncomp=2)
+    st, Pi = gu.run_pi(dp, ncomp=1)
+    assert st == 0
+    check_full(dp, Pi, ncomp=1)
+
+
+def test_device_scale_sampled():
+    prob = configs.DEVICE
+    dp = gu.DeviceProblem(prob, configs.SEED, ncomp=2)
+    st, Pi = gu.run_pi(dp)
+    assert st == 0
+    blocks = gu.sample_pi_blocks(prob, 99, n_a=2, n_w=3)
+    for c in range(2):
+        full = gu.pi_host(Pi, c, prob)
+        got = full[blocks[:, 0], blocks[:, 1], blocks[:, 2]]
+        want = gu.oracle_pi_blocks(dp, c, blocks)
+        e1, e2 = gu.rel_fro(got, want), gu.max_elem_rel(got, want)
+        print(f"  comp {c}: {len(blocks)} blocks rel_fro={e1:.3e} max_elem={e2:.3e}", flush=True)
+        assert e1 <= TOL and e2 <= TOL, (c, e1, e2)
+        # every block holds finite values and the diagonal is minus the neighbour sum
+        assert np.isfinite(full).all()
+        d = full[..., prob.NB, :, :] + full[..., :prob.NB, :, :].sum(axis=-3)
+        assert np.linalg.norm(d) <= 1e-13 * np.linalg.norm(full)
+
+
+def test_bad_neighbour_and_unsupported():
+    from paper_1912_08810_amd import sse
+    import torch
+    prob = configs.Problem(NA=5, NB=2, Norb=3, Nkz=2, Nqz=2, NE=8, Nw=2)
+    neigh = np.array([[1, 2], [0, 7], [3, 4], [2, 0], [1, 3]], dtype=np.int32)
+    dp = gu.DeviceProblem(prob, 29, ncomp=2, neigh=np.where(neigh < 5, neigh, 0))
+    dp.neigh.copy_(torch.from_numpy(neigh).cuda())
+    st, _ = gu.run_pi(dp)
+    assert st == sse.ERR_NEIGH
+    big = sse.sse_plan(sse.make_desc(4, 2, 17, 2, 2, 8, 2, ncomp=2), np.array([1, 2]))
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    assert sse.sse_pi_compute(big, 1, 1, 1, 1, ws, None, check=False) == sse.ERR_UNSUPPORTED
+    c64 = sse.sse_plan(sse.make_desc(4, 2, 3, 2, 2, 8, 2, ncomp=2, prec=sse.BF16X3),
+                       np.array([1, 2]))
+    assert sse.sse_pi_compute(c64, 1, 1, 1, 1, ws, None, check=False) == sse.ERR_UNSUPPORTED

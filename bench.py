@@ -39,6 +39,9 @@ def parse():
                          "fp64c64 = binary64 arithmetic on complex64 storage")
     ap.add_argument("--only", default="",
                     help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
+    ap.add_argument("--pi-steps", type=int, default=2,
+                    help="timed steps of the phonon self-energy (Eqs. (4)-(5)) at device "
+                         "scale, both components (0 = skip)")
     ap.add_argument("--batch", default="fp64,bf16x3",
                     help="precisions of the 48-instance batched run ('' = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=200.0)
@@ -157,6 +160,43 @@ def cpu_baseline(prob, seed, target_s):
                      "blocks": len(sub), "s": round(t1, 2)},
         "cpu_model": cpu_model,
     }
+
+
+def pi_section(args, torch, sse, prob, seed, DeviceProblem, log):
+    """The phonon self-energy of the device-scale problem, both components,
+    binary64: one step = one sse_pi_compute.  Its algorithmic flops per
+    component equal the electron self-energy's (9 (i, j) complex multiply-adds
+    per orbital pair and (k, e, q, w, a, b); 48 Norb^3 per (k, e, a, b) for the
+    two dH products)."""
+    dp = DeviceProblem(prob, seed, ncomp=2)
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                         ncomp=2, prec=sse.FP64)
+    plan = sse.sse_plan(desc, prob.shifts())
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    Pi = torch.empty(2, sse.pi_elems(desc) * 2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    sse.sse_pi_compute(plan, dp.neigh, dp.dH, dp.G, Pi, ws, stream)
+    torch.cuda.synchronize()
+    times = []
+    for i in range(args.pi_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sse.sse_pi_compute(plan, dp.neigh, dp.dH, dp.G, Pi, ws, stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        log(f"pi step {i}: {times[-1] * 1e3:.1f} ms")
+    del dp, Pi, ws
+    torch.cuda.empty_cache()
+    med = statistics.median(times)
+    tf = prob.flops() / (med / 2) / 1e12
+    return {"value": round(2 * prob.flops() / med / 1e9, 1), "unit": "GFLOP/s",
+            "ms_per_step": round(med * 1e3, 3), "steps": len(times), "storage": "complex128",
+            "workload": "Pi lesser+greater [7, 30, 1024, 5, 3, 3] from G [2, 7, 1000, 1024, "
+                        "10, 10], NB=4, s_w=w+1",
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                         "kernel": "k_pi_fp64"}}
 
 
 def batch_section(args, torch, sse, configs, DeviceProblem, log):
@@ -458,7 +498,9 @@ def main():
     progress(f"fp64: {med*1e3:.1f} ms/step")
     log = progress
     if args.only:
-        args.batch, args.serving_jobs = "", 0
+        args.batch, args.serving_jobs, args.pi_steps = "", 0, 0
+    if args.pi_steps > 0:
+        out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, log)
     if args.batch:
         out["batch"] = batch_section(args, torch, sse, configs, DeviceProblem, log)
     if args.serving_jobs > 0:

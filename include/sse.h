@@ -225,6 +225,39 @@ sse_status sse_pi_submit(sse_plan_t plan, const int32_t *neigh, const double *dH
 sse_status sse_pi_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
                           void *Pi, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The combination of phonon Green's function blocks that Eq. (3) sums over
+ * (Sec. 2; Sec. 4.2 names it as the kernel's input), for a single-instance
+ * plan (its sizes, ncomp and storage: complex128 for SSE_FP64, complex64
+ * otherwise):
+ *
+ *   Dt[q, w, a, b, i, j] = D_ba - D_bb - D_aa + D_ab      (entry (i, j) of each block)
+ *
+ * D [ncomp][Nqz, Nw, NA, NB + 1, 3, 3] holds, per atom a, the blocks
+ * D_a,neigh[a, b] in slots b < NB and the diagonal block D_aa in slot NB (the
+ * layout of Pi); for f = neigh[a, b], D_ab = D[.., a, b], D_bb = D[.., f, NB],
+ * D_aa = D[.., a, NB] and D_ba = D[.., f, r] with r the first slot of f's row
+ * holding a.  The sum is formed left to right in binary64.  Dt
+ * [ncomp][Nqz, Nw, NA, NB, 3, 3] is overwritten.  The table must be symmetric:
+ * a neighbour index outside [0, NA), or an atom missing from the row of one of
+ * its neighbours, gives SSE_ERR_NEIGH (at poll) and zero blocks there.
+ * Workspace: at least 256 + 4 NA NB bytes (the reverse map).
+ */
+sse_status sse_dtilde_submit(sse_plan_t plan, const int32_t *neigh, const void *D, void *Dt,
+                             void *workspace, size_t workspace_bytes, void *stream,
+                             uint64_t *ticket);
+
+/*
+ * Retarded component from the lesser and greater ones, (X> - X<) / 2 (Sec. 2,
+ * after Eq. (5); the same relation for Sigma and Pi), elementwise over the
+ * plan's tensor: which = 0: X = Sigma [2][Nkz, NE, NA, Norb, Norb] (storage of
+ * the plan's precision), XR [Nkz, NE, NA, Norb, Norb]; which = 1: X = Pi
+ * [2][Nqz, Nw, NA, NB + 1, 3, 3] complex128 (SSE_FP64 plans), XR one component.
+ * Enqueued on `stream`; returns once enqueued (no ticket: nothing is checked on
+ * the device).
+ */
+sse_status sse_retarded(sse_plan_t plan, int32_t which, const void *X, void *XR, void *stream);
+
 /* SSE_PENDING while the submission runs, else its final status (the ticket is
  * then released; polling it again gives SSE_ERR_ARG). */
 sse_status sse_poll(uint64_t ticket);

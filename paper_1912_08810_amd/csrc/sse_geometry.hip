@@ -3,6 +3,7 @@
 // bytes and workspace sizes.  Host code only (also built by the host-side
 // runtime test with a stand-in HIP header).
 #include <algorithm>
+#include <vector>
 
 #include "sse_internal.h"
 #include "sse_mfma.h"
@@ -113,6 +114,59 @@ size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int No
     if (prec == SSE_BF16X3)
         b += (size_t)Nkz * NE * NA * Norb * Norb * 8;
     return b;
+}
+
+// Tap chunks of the phonon kernel (sse_pi.hip): taps sorted by increasing
+// shift, cut where a chunk would exceed the workgroup's tap groups or its ring
+// of rows would not fit the LDS budget.
+PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw)
+{
+    PiGeom gm{};
+    const int NN = Norb * Norb;
+    const int kNT = pik::kNT;
+    std::vector<int> order(Nw);
+    for (int w = 0; w < Nw; ++w)
+        order[w] = w;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return w_shift[x] < w_shift[y]; });
+    for (int t = 0; t < Nw; ++t) {
+        gm.tw[t] = order[t];
+        gm.ts[t] = w_shift[order[t]];
+    }
+    // LDS per workgroup: ring R rows + Zt (9) + U (3) + Y (1) blocks of complex128,
+    // dH (3 blocks of binary64); two workgroups per CU if the taps fit, else one.
+    const size_t fixed = (size_t)NN * 16 * 13 + (size_t)NN * 8 * 3;
+    const size_t per_row = (size_t)NN * 16;
+    int rmax = (int)(((size_t)pik::kLdsBudget - std::min(fixed, (size_t)pik::kLdsBudget)) / per_row);
+    gm.lds_budget = pik::kLdsBudget;
+    if (rmax < std::min(gm.ts[Nw - 1] - gm.ts[0] + 1, 16)) {
+        rmax = (int)(((size_t)pik::kLdsBudgetOne - std::min(fixed, (size_t)pik::kLdsBudgetOne)) /
+                     per_row);
+        gm.lds_budget = pik::kLdsBudgetOne;
+    }
+    gm.R = 0;
+    gm.nchunk = 0;
+    int t = 0;
+    while (t < Nw) {
+        int e = t + 1;
+        while (e < Nw && e - t < pik::kMaxGroups * kNT && gm.ts[e] - gm.ts[t] + 1 <= rmax)
+            ++e;
+        gm.cb[gm.nchunk] = t;
+        int groups = (e - t + kNT - 1) / kNT;
+        int pow2 = 1;
+        while (pow2 < groups)
+            pow2 <<= 1;
+        gm.cg[gm.nchunk] = pow2;
+        gm.R = std::max(gm.R, gm.ts[e - 1] - gm.ts[t] + 1);
+        ++gm.nchunk;
+        t = e;
+    }
+    gm.cb[gm.nchunk] = Nw;
+    gm.lds_bytes = (size_t)gm.R * per_row + fixed;
+    // the final reduction reuses the ring for 4 waves x 9 x kNT complex values
+    gm.lds_bytes = std::max(gm.lds_bytes, (size_t)4 * kNF * kNT * 16);
+    gm.ok = rmax >= 1;
+    return gm;
 }
 
 }  // namespace sse

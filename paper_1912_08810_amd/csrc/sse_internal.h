@@ -270,6 +270,13 @@ hipError_t launch_validate_neigh(const int32_t *neigh, int64_t n, int32_t NA, ui
 
 constexpr uint32_t kStatusBadNeigh = 1u;
 constexpr uint32_t kStatusBadBlock = 2u;
+constexpr uint32_t kStatusAsymNeigh = 4u;  // an atom missing from its neighbour's row
+
+// D -> Dt and the retarded components (sse_dtilde.hip).
+hipError_t dtilde_launch(const void *D, void *Dt, const int32_t *neigh, int32_t *rmap,
+                         uint32_t *status, int64_t nqw, int32_t NA, int32_t NB, bool c64,
+                         hipStream_t s);
+hipError_t retarded_launch(const void *X, void *XR, int64_t n, bool c64, hipStream_t s);
 
 hipError_t check_launch(const CheckParams &p, double *out, hipStream_t s);
 

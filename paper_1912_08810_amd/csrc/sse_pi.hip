@@ -104,7 +104,7 @@ __device__ __forceinline__ void sandwich_second(const double *dHs, const double2
     }
 }
 
-__global__ __launch_bounds__(kBlock, 2) void k_pi_fp64(const PiParams p)
+__global__ __launch_bounds__(kBlock, 1) void k_pi_fp64(const PiParams p)
 {
     extern __shared__ double2 lds[];
     const int NN = p.NN, No = p.Norb, R = p.R;
@@ -306,55 +306,6 @@ __global__ void k_pi_diag(double2 *Pi, int64_t nqwa, int NB)
 }
 
 }  // namespace
-
-PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw)
-{
-    PiGeom gm{};
-    const int NN = Norb * Norb;
-    std::vector<int> order(Nw);
-    for (int w = 0; w < Nw; ++w)
-        order[w] = w;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return w_shift[x] < w_shift[y]; });
-    for (int t = 0; t < Nw; ++t) {
-        gm.tw[t] = order[t];
-        gm.ts[t] = w_shift[order[t]];
-    }
-    // LDS per workgroup: ring R rows + Zt (9) + U (3) + Y (1) blocks of complex128,
-    // dH (3 blocks of binary64); two workgroups per CU if the taps fit, else one.
-    const size_t fixed = (size_t)NN * 16 * 13 + (size_t)NN * 8 * 3;
-    const size_t per_row = (size_t)NN * 16;
-    int rmax = (int)(((size_t)pik::kLdsBudget - std::min(fixed, (size_t)pik::kLdsBudget)) / per_row);
-    gm.lds_budget = pik::kLdsBudget;
-    if (rmax < std::min(gm.ts[Nw - 1] - gm.ts[0] + 1, 16)) {
-        rmax = (int)(((size_t)pik::kLdsBudgetOne - std::min(fixed, (size_t)pik::kLdsBudgetOne)) /
-                     per_row);
-        gm.lds_budget = pik::kLdsBudgetOne;
-    }
-    gm.R = 0;
-    gm.nchunk = 0;
-    int t = 0;
-    while (t < Nw) {
-        int e = t + 1;
-        while (e < Nw && e - t < pik::kMaxGroups * kNT && gm.ts[e] - gm.ts[t] + 1 <= rmax)
-            ++e;
-        gm.cb[gm.nchunk] = t;
-        int groups = (e - t + kNT - 1) / kNT;
-        int pow2 = 1;
-        while (pow2 < groups)
-            pow2 <<= 1;
-        gm.cg[gm.nchunk] = pow2;
-        gm.R = std::max(gm.R, gm.ts[e - 1] - gm.ts[t] + 1);
-        ++gm.nchunk;
-        t = e;
-    }
-    gm.cb[gm.nchunk] = Nw;
-    gm.lds_bytes = (size_t)gm.R * per_row + fixed;
-    // the final reduction reuses the ring for 4 waves x 9 x kNT complex values
-    gm.lds_bytes = std::max(gm.lds_bytes, (size_t)4 * kNF * kNT * 16);
-    gm.ok = rmax >= 1;
-    return gm;
-}
 
 hipError_t pi_launch(const PiParams &p, size_t lds_bytes, hipStream_t s)
 {

@@ -722,6 +722,9 @@ static sse_status status_from_word(uint32_t hs)
         return fail(SSE_ERR_NEIGH, "a neighbour index is outside [0, NA)");
     if (hs & kStatusBadBlock)
         return fail(SSE_ERR_ARG, "sse_check_submit: a listed block is outside the output");
+    if (hs & kStatusAsymNeigh)
+        return fail(SSE_ERR_NEIGH, "the neighbour table is not symmetric: an atom is missing "
+                                   "from the row of one of its neighbours");
     if (hs != 0)
         return fail(SSE_ERR_DEVICE, "device status word 0x%x", hs);
     return SSE_OK;
@@ -930,6 +933,60 @@ sse_status sse_pi_compute(sse_plan_t plan, const int32_t *neigh, const double *d
     if (st != SSE_OK)
         return st;
     return sse_wait(t);
+}
+
+sse_status sse_dtilde_submit(sse_plan_t plan, const int32_t *neigh, const void *D, void *Dt,
+                             void *workspace, size_t workspace_bytes, void *stream,
+                             uint64_t *ticket)
+{
+    if (!plan || !ticket || !neigh || !D || !Dt)
+        return fail(SSE_ERR_ARG, "sse_dtilde_submit: NULL argument");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_dtilde_submit: needs a single-instance plan");
+    const sse_desc &d = plan->inst[0].d;
+    const size_t need = kStatusBytes + (size_t)4 * d.NA * d.NB;
+    if (!workspace || workspace_bytes < need)
+        return fail(SSE_ERR_ARG, "sse_dtilde_submit: workspace of %zu bytes needed", need);
+    hipStream_t s = (hipStream_t)stream;
+    Ticket tk;
+    sse_status st = ticket_acquire(&tk);
+    if (st != SSE_OK)
+        return st;
+    uint32_t *dstatus = (uint32_t *)workspace;
+    int32_t *rmap = (int32_t *)((char *)workspace + kStatusBytes);
+    const bool c64 = d.prec != SSE_FP64;
+    const size_t eb = c64 ? 8 : 16;
+    const int64_t nqw = (int64_t)d.Nqz * d.Nw;
+    const size_t d_in = (size_t)nqw * d.NA * (d.NB + 1) * kNF;
+    const size_t d_out = (size_t)nqw * d.NA * d.NB * kNF;
+    hipError_t e = launch_clear_status(dstatus, s);
+    for (int c = 0; c < d.ncomp && e == hipSuccess; ++c)
+        e = dtilde_launch((const char *)D + c * d_in * eb, (char *)Dt + c * d_out * eb, neigh,
+                          rmap, dstatus, nqw, d.NA, d.NB, c64, s);
+    if (e != hipSuccess) {
+        ticket_release(tk);
+        return hip_fail(e, "D~ kernel launch");
+    }
+    return ticket_finish_enqueue(tk, dstatus, sizeof(uint32_t), s, ticket);
+}
+
+sse_status sse_retarded(sse_plan_t plan, int32_t which, const void *X, void *XR, void *stream)
+{
+    if (!plan || !X || !XR)
+        return fail(SSE_ERR_ARG, "sse_retarded: NULL argument");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_retarded: needs a single-instance plan");
+    if (which != 0 && which != 1)
+        return fail(SSE_ERR_ARG, "sse_retarded: which must be 0 (Sigma) or 1 (Pi)");
+    const sse_desc &d = plan->inst[0].d;
+    if (which == 1 && d.prec != SSE_FP64)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_retarded: Pi is complex128 (SSE_FP64) only");
+    const int64_t n = which == 0 ? (int64_t)d.Nkz * d.NE * d.NA * d.Norb * d.Norb
+                                 : (int64_t)d.Nqz * d.Nw * d.NA * (d.NB + 1) * kNF;
+    hipError_t e = retarded_launch(X, XR, n, d.prec != SSE_FP64, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "retarded kernel launch");
+    return SSE_OK;
 }
 
 sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,

@@ -71,6 +71,8 @@ def _load():
     L.sse_compute_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.sse_pi_submit.argtypes = [vp, vp, vp, vp, vp, vp, c.c_size_t, vp, c.POINTER(c.c_uint64)]
     L.sse_pi_compute.argtypes = [vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
+    L.sse_dtilde_submit.argtypes = [vp, vp, vp, vp, vp, c.c_size_t, vp, c.POINTER(c.c_uint64)]
+    L.sse_retarded.argtypes = [vp, c.c_int32, vp, vp, vp]
     L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
                              c.POINTER(c.c_uint64)]
     L.sse_check_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_int32, c.c_double, vp, vp,
@@ -81,7 +83,8 @@ def _load():
     L.sse_plan_destroy.restype = None
     L.sse_last_error.restype = c.c_char_p
     for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_compute_noalloc, L.sse_submit,
-              L.sse_poll, L.sse_wait, L.sse_check_submit, L.sse_pi_submit, L.sse_pi_compute):
+              L.sse_poll, L.sse_wait, L.sse_check_submit, L.sse_pi_submit, L.sse_pi_compute,
+              L.sse_dtilde_submit, L.sse_retarded):
         f.restype = c.c_int
     return L
 
@@ -89,9 +92,9 @@ def _load():
 lib = _load()
 
 # Every symbol include/sse.h declares (checked by the CPU test of the library).
-EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_last_error",
-           "sse_pi_compute", "sse_pi_submit", "sse_plan", "sse_plan_batch", "sse_plan_destroy",
-           "sse_poll", "sse_submit", "sse_wait"]
+EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_dtilde_submit",
+           "sse_last_error", "sse_pi_compute", "sse_pi_submit", "sse_plan", "sse_plan_batch",
+           "sse_plan_destroy", "sse_poll", "sse_retarded", "sse_submit", "sse_wait"]
 NOALLOC_SCRATCH_BYTES = 32 << 20  # SSE_NOALLOC_SCRATCH_BYTES
 
 
@@ -204,6 +207,25 @@ def sse_pi_submit(plan: Plan, neigh, dH, G, Pi, workspace, stream=None) -> int:
                              _ptr(workspace), nbytes, _stream(stream), ctypes.byref(t)),
            "sse_pi_submit")
     return t.value
+
+
+def dtilde_workspace_bytes(desc) -> int:
+    return 256 + 4 * desc.NA * desc.NB
+
+
+def sse_dtilde_submit(plan: Plan, neigh, D, Dt, workspace, stream=None) -> int:
+    """D [ncomp][Nqz, Nw, NA, NB + 1, 3, 3] -> Dt [ncomp][Nqz, Nw, NA, NB, 3, 3]; a ticket."""
+    t = ctypes.c_uint64()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib.sse_dtilde_submit(plan.handle, _ptr(neigh), _ptr(D), _ptr(Dt), _ptr(workspace),
+                                 nbytes, _stream(stream), ctypes.byref(t)), "sse_dtilde_submit")
+    return t.value
+
+
+def sse_retarded(plan: Plan, which: int, X, XR, stream=None, check=True) -> int:
+    """XR = (X[1] - X[0]) / 2; which 0 = Sigma, 1 = Pi."""
+    st = lib.sse_retarded(plan.handle, which, _ptr(X), _ptr(XR), _stream(stream))
+    return _check(st, "sse_retarded") if check else st
 
 
 def _args(items):

@@ -131,6 +131,20 @@ def neigh(seed: int, NA: int, NB: int) -> np.ndarray:
     return out
 
 
+def neigh_symmetric(seed: int, NA: int, NB: int) -> np.ndarray:
+    """A symmetric neighbour table: the atoms on a ring in a seeded random
+    order, each joined to the NB/2 nearest atoms on either side (NB even,
+    NA > NB), so atom a is in the row of each of its neighbours.  Column order
+    per row: +1, -1, +2, -2, ... along the ring."""
+    if NB % 2 or NA <= NB:
+        raise ValueError("need an even NB and NA > NB")
+    order = np.random.default_rng(seed).permutation(NA)
+    pos = np.argsort(order)
+    offs = [o for d in range(1, NB // 2 + 1) for o in (d, -d)]
+    return np.array([[order[(pos[a] + o) % NA] for o in offs] for a in range(NA)],
+                    dtype=np.int32)
+
+
 def dH(seed: int, NA: int, NB: int, Norb: int, N3D: int = 3) -> np.ndarray:
     out = np.empty((NA, NB, N3D, Norb, Norb), dtype=np.float64)
     _hostlib().ssegen_host_dH(seed, out.size, _ptr(out))

@@ -78,6 +78,27 @@ int main() {
     if (sse_compute_noalloc(pbig, neigh.data(), dH.data(), G.data(), D.data(), S.data(), nullptr) != SSE_ERR_UNSUPPORTED) return 11;
     sse_plan_destroy(pbig);
   }
+  {
+    // phonon self-energy, D~ and the retarded relation through the C ABI
+    sse_desc pd = d; pd.prec = SSE_FP64; pd.ncomp = 2; pd.Norb = 4; pd.Nw = 8;
+    int32_t psh[8] = {3, -2, 1, 5, 0, 7, 2, 2};
+    sse_plan_t pp; size_t wsp;
+    if (sse_plan(&pd, psh, &pp, &wsp)) return 12;
+    std::vector<char> PW(256 + 4 * pd.NA * pd.NB);
+    uint64_t t1, t2;
+    if (sse_pi_submit(pp, neigh.data(), dH.data(), G.data(), S.data(), PW.data(), PW.size(), nullptr, &t1)) { printf("pi: %s\n", sse_last_error()); return 13; }
+    if (sse_wait(t1)) return 14;
+    if (sse_dtilde_submit(pp, neigh.data(), D.data(), S.data(), PW.data(), PW.size(), nullptr, &t2)) { printf("dtilde: %s\n", sse_last_error()); return 15; }
+    if (sse_wait(t2)) return 16;
+    if (sse_dtilde_submit(pp, neigh.data(), D.data(), S.data(), PW.data(), 256, nullptr, &t2) != SSE_ERR_ARG) return 17;
+    if (sse_retarded(pp, 1, G.data(), S.data(), nullptr)) return 18;
+    if (sse_retarded(pp, 2, G.data(), S.data(), nullptr) != SSE_ERR_ARG) return 19;
+    sse_plan_destroy(pp);
+    pd.Norb = 17;
+    if (sse_plan(&pd, psh, &pp, &wsp)) return 20;
+    if (sse_pi_submit(pp, neigh.data(), dH.data(), G.data(), S.data(), PW.data(), PW.size(), nullptr, &t1) != SSE_ERR_UNSUPPORTED) return 21;
+    sse_plan_destroy(pp);
+  }
   printf("OK\n");
   return 0;
 }

@@ -99,6 +99,11 @@ typedef struct {
                            window); 0 = as many as the window holds.  Under
                            SSE_FP32/SSE_BF16X3 it bounds the fp32 part of the tap sum;
                            in every precision it is a tuning parameter.  >= 0 */
+    int32_t dt_antiherm; /* 0: general Dt.  1: Dt anti-Hermitian per 3 x 3 block
+                            (Dt_ji = -conj(Dt_ij), as the lesser/greater phonon Green's
+                            function is): only Re/Im of the entries i < j and Im of the
+                            diagonal are read, which halves the tap arithmetic.  SSE_FP64
+                            and SSE_FP64C64 only (SSE_ERR_UNSUPPORTED otherwise). */
     double alpha_re, alpha_im; /* prefactor; Eq. (3) is alpha = i (0 + 1i) */
 } sse_desc;
 

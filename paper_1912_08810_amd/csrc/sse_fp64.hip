@@ -55,6 +55,51 @@ __device__ __forceinline__ void cmac(double &accr, double &acci, double dr, doub
     acci = fma(di, gr, acci);
 }
 
+// One tap's update of the nine filter accumulators of one position.  General
+// D~: acc_x += D~_x g for the nine (i, j).  Anti-Hermitian D~ (D~_ji =
+// -conj(D~_ij), so D~_ii = i Im D~_ii): slot ij (i < j) gathers U_ij += Re D~_ij g,
+// slot ji gathers V_ij += Im D~_ij g, and slot ii gathers V_ii += Im D~_ii g
+// -- 18 instead of 36 FMAs; ah_finish turns them into Gh_ij = U + iV,
+// Gh_ji = -U + iV, Gh_ii = i V.
+template <bool AH>
+__device__ __forceinline__ void tap_update(double (&ar)[kNF], double (&ai)[kNF],
+                                           const double2 (&d)[kNF], double2 g)
+{
+    if constexpr (!AH) {
+#pragma unroll
+        for (int x = 0; x < kNF; ++x)
+            cmac(ar[x], ai[x], d[x].x, d[x].y, g.x, g.y);
+    } else {
+        constexpr int up[3] = {1, 2, 5}, lo[3] = {3, 6, 7}, dg[3] = {0, 4, 8};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ar[up[k]] = fma(d[up[k]].x, g.x, ar[up[k]]);
+            ai[up[k]] = fma(d[up[k]].x, g.y, ai[up[k]]);
+            ar[lo[k]] = fma(d[up[k]].y, g.x, ar[lo[k]]);
+            ai[lo[k]] = fma(d[up[k]].y, g.y, ai[lo[k]]);
+            ar[dg[k]] = fma(d[dg[k]].y, g.x, ar[dg[k]]);
+            ai[dg[k]] = fma(d[dg[k]].y, g.y, ai[dg[k]]);
+        }
+    }
+}
+
+// Anti-Hermitian mode: (U, V) accumulators -> the nine filtered blocks.
+__device__ __forceinline__ void ah_finish(double (&ar)[kNF], double (&ai)[kNF])
+{
+    constexpr int up[3] = {1, 2, 5}, lo[3] = {3, 6, 7}, dg[3] = {0, 4, 8};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double ur = ar[up[k]], ui = ai[up[k]], vr = ar[lo[k]], vi = ai[lo[k]];
+        ar[up[k]] = ur - vi;
+        ai[up[k]] = ui + vr;
+        ar[lo[k]] = -ur - vi;
+        ai[lo[k]] = -ui + vr;
+        const double wr = ar[dg[k]], wi = ai[dg[k]];
+        ar[dg[k]] = -wi;
+        ai[dg[k]] = wr;
+    }
+}
+
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
 template <typename T> __device__ __forceinline__ T from_d2(double x, double y);
@@ -75,7 +120,7 @@ __device__ __attribute__((aligned(16))) uint32_t g_zero16[4] = {0u, 0u, 0u, 0u};
 // memory), ptr its tensors.
 // T is the storage type of G, D~ and Sigma (complex128, or complex64 promoted to
 // binary64 on load); all arithmetic is binary64.
-template <typename T>
+template <typename T, bool AH>
 __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const TensorPtrs &ptr, int a,
                                           int k, int et, double2 *lds)
 {
@@ -199,9 +244,7 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int r = 0; r < kR; ++r)
-#pragma unroll
-                            for (int x = 0; x < kNF; ++x)
-                                cmac(ar[r][x], ai[r][x], cur[x].x, cur[x].y, g[r].x, g[r].y);
+                            tap_update<AH>(ar[r], ai[r], cur, g[r]);
                         sh = sh2;
                         wn = wn2;
                         ++t;
@@ -223,16 +266,17 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                         da[x] = to_d2(dpa[x]);
                     const double2 *wpa = lds + tid + (smax - p.taps.s[t]) * NN;
 #pragma unroll
-                    for (int r = 0; r < kR; ++r) {
-                        const double2 ga = wpa[r * kBlock];
-#pragma unroll
-                        for (int x = 0; x < kNF; ++x)
-                            cmac(ar[r][x], ai[r][x], da[x].x, da[x].y, ga.x, ga.y);
-                    }
+                    for (int r = 0; r < kR; ++r)
+                        tap_update<AH>(ar[r], ai[r], da, wpa[r * kBlock]);
                 }
             }
         }
 
+        if constexpr (AH) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r)
+                ah_finish(ar[r], ai[r]);
+        }
         // ---- sandwich: Sigma += sum_ij dH_i Gh_ij dH_j^T for this neighbour
         __syncthreads();  // window reads done; LDS becomes scratch
         const double *Ag = ptr.dH + ((size_t)a * p.NB + b) * kN3D * NN;
@@ -324,7 +368,7 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
     }
 }
 
-template <typename T>
+template <typename T, bool AH>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
 {
     extern __shared__ double2 lds[];
@@ -334,13 +378,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64(const Fp64Params p)
     const int et = (int)(L % p.n_etiles);
     const int a = (int)(L / p.n_etiles);
     const TensorPtrs ptr{p.neigh, p.dH, p.G, p.D, p.Sigma};
-    fp64_tile<T>(ro(&p), ptr, a, k, et, lds);
+    fp64_tile<T, AH>(ro(&p), ptr, a, k, et, lds);
 }
 
 // Persistent form: a fixed grid pulls tiles from the batch's work queues
 // (one queue per XCD, then the others) until all are taken; the next tile's
 // ticket is taken while the current tile runs.
-template <typename T>
+template <typename T, bool AH>
 __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLaunch bl)
 {
     extern __shared__ double2 lds[];
@@ -360,8 +404,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sse_fp64_persistent(const BatchLa
         long long ticket = 0;
         if (threadIdx.x == 0)
             ticket = pull_take(bl, home, s_st);
-        fp64_tile<T>(ro(reinterpret_cast<const Fp64Params *>(bl.params)) + inst, bl.ptr[inst], a,
-                     k, et, lds);
+        fp64_tile<T, AH>(ro(reinterpret_cast<const Fp64Params *>(bl.params)) + inst,
+                         bl.ptr[inst], a, k, et, lds);
         if (threadIdx.x == 0)
             pull_resolve(bl, home, ticket, s_st, s_tile);
         __syncthreads();
@@ -382,43 +426,50 @@ static hipError_t set_lds_attr(K kernel, bool &done)
     return e;
 }
 
-hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, size_t lds_bytes,
-                                  hipStream_t s)
+template <typename T, bool AH>
+static hipError_t persistent_launch_as(const BatchLaunch &bl, int grid, size_t lds_bytes,
+                                       hipStream_t s)
 {
-    static bool done[2] = {false, false};
-    hipError_t e = c64 ? set_lds_attr(k_sse_fp64_persistent<float2>, done[1])
-                       : set_lds_attr(k_sse_fp64_persistent<double2>, done[0]);
+    static bool done = false;
+    hipError_t e = set_lds_attr(k_sse_fp64_persistent<T, AH>, done);
     if (e != hipSuccess)
         return e;
-    if (c64) {
-        (void)hipGetLastError();
-        hipLaunchKernelGGL(k_sse_fp64_persistent<float2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
-    } else {
-        (void)hipGetLastError();
-        hipLaunchKernelGGL(k_sse_fp64_persistent<double2>, dim3(grid), dim3(kBlock), lds_bytes, s, bl);
-    }
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_sse_fp64_persistent<T, AH>), dim3(grid), dim3(kBlock), lds_bytes, s, bl);
     return hipGetLastError();
 }
 
-hipError_t fp64_launch(const Fp64Params &p, bool c64, size_t lds_bytes, hipStream_t s)
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, bool ah, int grid,
+                                  size_t lds_bytes, hipStream_t s)
+{
+    if (c64)
+        return ah ? persistent_launch_as<float2, true>(bl, grid, lds_bytes, s)
+                  : persistent_launch_as<float2, false>(bl, grid, lds_bytes, s);
+    return ah ? persistent_launch_as<double2, true>(bl, grid, lds_bytes, s)
+              : persistent_launch_as<double2, false>(bl, grid, lds_bytes, s);
+}
+
+template <typename T, bool AH>
+static hipError_t launch_as(const Fp64Params &p, size_t lds_bytes, hipStream_t s)
+{
+    static bool done = false;
+    hipError_t e = set_lds_attr(k_sse_fp64<T, AH>, done);
+    if (e != hipSuccess)
+        return e;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_sse_fp64<T, AH>), dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
+    return hipGetLastError();
+}
+
+hipError_t fp64_launch(const Fp64Params &p, bool c64, bool ah, size_t lds_bytes, hipStream_t s)
 {
     if (p.n_wg <= 0)
         return hipSuccess;
     if (p.n_wg > 0x7fffffffLL)
         return hipErrorInvalidConfiguration;
-    static bool done[2] = {false, false};
-    hipError_t e = c64 ? set_lds_attr(k_sse_fp64<float2>, done[1])
-                       : set_lds_attr(k_sse_fp64<double2>, done[0]);
-    if (e != hipSuccess)
-        return e;
-    if (c64) {
-        (void)hipGetLastError();
-        hipLaunchKernelGGL(k_sse_fp64<float2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
-    } else {
-        (void)hipGetLastError();
-        hipLaunchKernelGGL(k_sse_fp64<double2>, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
-    }
-    return hipGetLastError();
+    if (c64)
+        return ah ? launch_as<float2, true>(p, lds_bytes, s) : launch_as<float2, false>(p, lds_bytes, s);
+    return ah ? launch_as<double2, true>(p, lds_bytes, s) : launch_as<double2, false>(p, lds_bytes, s);
 }
 
 }  // namespace sse

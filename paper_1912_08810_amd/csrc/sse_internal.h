@@ -257,9 +257,10 @@ struct TileGeom {
 // Host helpers (sse_fp64.hip).
 TileGeom fp64_geometry(int Norb, int NE, const TapTable &taps_unchunked, int te_request,
                        int chunk_cap, TapTable *taps_out);
-hipError_t fp64_launch(const Fp64Params &p, bool c64, size_t lds_bytes, hipStream_t s);
-hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, int grid, size_t lds_bytes,
-                                  hipStream_t s);
+// ah: D~ anti-Hermitian per 3 x 3 block (only i <= j read; half the tap FMAs).
+hipError_t fp64_launch(const Fp64Params &p, bool c64, bool ah, size_t lds_bytes, hipStream_t s);
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool c64, bool ah, int grid,
+                                  size_t lds_bytes, hipStream_t s);
 
 
 // Auxiliary kernels (sse_aux.hip).

@@ -134,6 +134,12 @@ sse_status check_desc(const sse_desc *d, const int32_t *w_shift)
         return fail(SSE_ERR_SHAPE, "sse_plan: ncomp=%d, must be 1 or 2", d->ncomp);
     if (d->tile_e < 0 || d->chunk_taps < 0)
         return fail(SSE_ERR_ARG, "sse_plan: tile_e and chunk_taps must be >= 0");
+    if (d->dt_antiherm != 0 && d->dt_antiherm != 1)
+        return fail(SSE_ERR_ARG, "sse_plan: dt_antiherm must be 0 or 1");
+    if (d->dt_antiherm && d->prec != SSE_FP64 && d->prec != SSE_FP64C64)
+        return fail(SSE_ERR_UNSUPPORTED,
+                    "sse_plan: dt_antiherm is a binary64-kernel mode (the matrix-core forms' tap "
+                    "products are dense real GEMMs whose row count it would not change)");
     for (int w = 0; w < d->Nw; ++w)
         if (w_shift[w] <= -d->NE || w_shift[w] >= d->NE)
             return fail(SSE_ERR_SHAPE, "sse_plan: |w_shift[%d]|=%d not below NE=%d", w, w_shift[w],
@@ -232,7 +238,7 @@ sse_status enqueue_instance(const Instance &I, const sse_args &a, uint32_t *dsta
             p.alpha_im = d.alpha_im;
             p.taps = I.taps;
             fill_tap_pairs(p);
-            e = fp64_launch(p, d.prec == SSE_FP64C64, I.geom.lds_bytes, s);
+            e = fp64_launch(p, d.prec == SSE_FP64C64, d.dt_antiherm != 0, I.geom.lds_bytes, s);
             if (e != hipSuccess)
                 return hip_fail(e, "fp64 kernel launch");
         } else {
@@ -477,7 +483,8 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
         if (e != hipSuccess)
             return hip_fail(e, "counter clear launch");
         if (fp64_arith(d0.prec))
-            e = fp64_persistent_launch(bl, d0.prec == SSE_FP64C64, P->grid, P->lds_bytes, s);
+            e = fp64_persistent_launch(bl, d0.prec == SSE_FP64C64, d0.dt_antiherm != 0, P->grid,
+                                       P->lds_bytes, s);
         else
             e = mfma_persistent_launch(d0.prec, bl, P->grid, P->lds_bytes, s);
         if (e != hipSuccess)
@@ -532,9 +539,10 @@ sse_status sse_plan_batch(const sse_desc *descs, const int32_t *const *w_shift, 
     for (int t = 0; t < n; ++t) {
         const sse_desc &d0 = descs[0], &dt = descs[t];
         if (dt.Norb != d0.Norb || dt.ncomp != d0.ncomp || dt.prec != d0.prec ||
-            dt.alpha_re != d0.alpha_re || dt.alpha_im != d0.alpha_im || dt.N3D != d0.N3D) {
+            dt.alpha_re != d0.alpha_re || dt.alpha_im != d0.alpha_im || dt.N3D != d0.N3D ||
+            dt.dt_antiherm != d0.dt_antiherm) {
             delete p;
-            return fail(SSE_ERR_ARG, "sse_plan_batch: instance %d differs in Norb/ncomp/prec/alpha",
+            return fail(SSE_ERR_ARG, "sse_plan_batch: instance %d differs in Norb/ncomp/prec/alpha/dt_antiherm",
                         t);
         }
         sse_status st = build_instance(&descs[t], w_shift[t], &p->inst[t]);

@@ -26,7 +26,8 @@ class sse_desc(ctypes.Structure):
                 ("N3D", ctypes.c_int32), ("Nkz", ctypes.c_int32), ("Nqz", ctypes.c_int32),
                 ("NE", ctypes.c_int32), ("Nw", ctypes.c_int32), ("ncomp", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("tile_e", ctypes.c_int32),
-                ("chunk_taps", ctypes.c_int32), ("alpha_re", ctypes.c_double),
+                ("chunk_taps", ctypes.c_int32), ("dt_antiherm", ctypes.c_int32),
+                ("alpha_re", ctypes.c_double),
                 ("alpha_im", ctypes.c_double)]
 
 
@@ -125,10 +126,10 @@ def _stream(s):
 
 
 def make_desc(NA, NB, Norb, Nkz, Nqz, NE, Nw, ncomp=1, prec=FP64, alpha=1j, N3D=3, tile_e=0,
-              chunk_taps=0):
+              chunk_taps=0, dt_antiherm=0):
     alpha = complex(alpha)
     return sse_desc(NA, NB, Norb, N3D, Nkz, Nqz, NE, Nw, ncomp, prec, tile_e, chunk_taps,
-                    alpha.real, alpha.imag)
+                    int(dt_antiherm), alpha.real, alpha.imag)
 
 
 class Plan:

@@ -75,8 +75,8 @@ static void check_pulls(const BatchLaunch &bl, int grid)
     for (int g : {1, 3, 8, 13, 64, grid})
         simulate_pulls<Params>(bl, n_inst, g);
 }
-hipError_t fp64_launch(const Fp64Params &, bool, size_t, hipStream_t) { return hipSuccess; }
-hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool, int grid, size_t, hipStream_t)
+hipError_t fp64_launch(const Fp64Params &, bool, bool, size_t, hipStream_t) { return hipSuccess; }
+hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool, bool, int grid, size_t, hipStream_t)
 {
     check_pulls<Fp64Params>(bl, grid);
     return hipSuccess;

@@ -34,9 +34,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16x3,fp64c64",
+    ap.add_argument("--forms", default="fp32,bf16x3,fp64c64,fp64ah",
                     help="precision forms timed after the binary64 headline ('' = none); "
-                         "fp64c64 = binary64 arithmetic on complex64 storage")
+                         "fp64c64 = binary64 arithmetic on complex64 storage; fp64ah = "
+                         "binary64 with the anti-Hermitian D~ mode (half the tap work)")
+    ap.add_argument("--aux-steps", type=int, default=5,
+                    help="timed steps of the D -> D~ and retarded passes at device scale "
+                         "(0 = skip)")
     ap.add_argument("--only", default="",
                     help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
     ap.add_argument("--pi-steps", type=int, default=2,
@@ -197,6 +201,64 @@ def pi_section(args, torch, sse, prob, seed, DeviceProblem, log):
             "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
                          "kernel": "k_pi_fp64"}}
+
+
+def aux_section(args, torch, sse, prob, log):
+    """The memory-bound passes either side of the kernels at device scale, both
+    components, complex128: D [2, 7, 30, 1024, 5, 3, 3] -> D~ (reverse neighbour
+    map on a symmetric table) and Sigma< / Sigma> -> Sigma^R.  Roofline: HBM,
+    algorithmic bytes = read each input once, write each output once."""
+    import numpy as np
+    import ssegen
+    nqw = prob.Nqz * prob.Nw
+    d_in = nqw * prob.NA * (prob.NB + 1) * 9
+    d_out = nqw * prob.NA * prob.NB * 9
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                         ncomp=2)
+    plan = sse.sse_plan(desc, prob.shifts())
+    neigh = torch.from_numpy(ssegen.neigh_symmetric(configs_seed(), prob.NA, prob.NB)).cuda()
+    D = torch.randn(2, 2 * d_in, dtype=torch.float64, device="cuda")
+    Dt = torch.empty(2, 2 * d_out, dtype=torch.float64, device="cuda")
+    ws = torch.empty(sse.dtilde_workspace_bytes(desc), dtype=torch.uint8, device="cuda")
+    S = torch.randn(2, 2 * prob.g_elems(), dtype=torch.float64, device="cuda")
+    SR = torch.empty(2 * prob.g_elems(), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.aux_steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return statistics.median(ts)
+
+    t_dt = timed(lambda: sse.sse_wait(sse.sse_dtilde_submit(plan, neigh, D, Dt, ws, stream)))
+    t_r = timed(lambda: sse.sse_retarded(plan, 0, S, SR, stream))
+    b_dt = 2 * 16 * (d_in + d_out) + prob.NA * prob.NB * 4
+    b_r = 3 * 16 * prob.g_elems()
+    log(f"aux: D~ {t_dt*1e3:.3f} ms, Sigma^R {t_r*1e3:.3f} ms")
+    del D, Dt, S, SR, ws
+    torch.cuda.empty_cache()
+
+    def roof(b, t, kern):
+        gbs = b / t / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "kernel": kern}
+
+    return {"dtilde": {"ms": round(t_dt * 1e3, 4), "bytes": b_dt,
+                       "roofline": roof(b_dt, t_dt, "k_reverse_map + k_dtilde")},
+            "retarded_sigma": {"ms": round(t_r * 1e3, 4), "bytes": b_r,
+                               "roofline": roof(b_r, t_r, "k_retarded")}}
+
+
+def configs_seed():
+    from paper_1912_08810_amd import configs
+    return configs.SEED
 
 
 def batch_section(args, torch, sse, configs, DeviceProblem, log):
@@ -388,10 +450,10 @@ def main():
     seed = configs.SEED
     ncomp = 2
 
-    def time_form(prec, fp32, scaled):
+    def time_form(prec, fp32, scaled, antiherm=0):
         dp = DeviceProblem(prob, seed, ncomp=ncomp, fp32=fp32, scaled=scaled)
         desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
-                             ncomp=ncomp, prec=prec)
+                             ncomp=ncomp, prec=prec, dt_antiherm=antiherm)
         plan = sse.sse_plan(desc, prob.shifts())
         ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
         stream = torch.cuda.current_stream()
@@ -437,6 +499,23 @@ def main():
         forms = [args.only] if args.only != "fp64" else []
     form_out = {}
     for name in forms:
+        if name == "fp64ah":
+            # binary64, complex128 inputs of the headline; D~ is anti-Hermitian per block
+            ft, _ = time_form(sse.FP64, False, False, antiherm=1)
+            fm = statistics.median(ft)
+            fl = prob.flops(antiherm=True)
+            tf = fl / (fm / ncomp) / 1e12
+            form_out[name] = {
+                "value": round(fl * ncomp / fm / 1e9, 1), "unit": "GFLOP/s",
+                "ms_per_step": round(fm * 1e3, 3), "ms_per_step_ci95": round(ci95(ft) * 1e3, 3),
+                "storage": "complex128", "flops_per_component": fl,
+                "inputs": "D~ anti-Hermitian per 3x3 block (dt_antiherm=1: tap work halved)",
+                "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                             "kernel": "k_sse_fp64<complex128, antiherm>"},
+                "speedup_vs_fp64": None}
+            progress(f"form {name}: {fm*1e3:.1f} ms/step")
+            continue
         prec = {"fp32": sse.FP32, "bf16x3": sse.BF16X3, "fp64c64": sse.FP64C64}[name]
         ft, _ = time_form(prec, True, True)
         fm = statistics.median(ft)
@@ -501,6 +580,8 @@ def main():
         args.batch, args.serving_jobs, args.pi_steps = "", 0, 0
     if args.pi_steps > 0:
         out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, log)
+    if args.aux_steps > 0 and not args.only:
+        out["aux"] = aux_section(args, torch, sse, prob, log)
     if args.batch:
         out["batch"] = batch_section(args, torch, sse, configs, DeviceProblem, log)
     if args.serving_jobs > 0:

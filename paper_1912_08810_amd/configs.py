@@ -51,9 +51,13 @@ class Problem:
         return (4 * self.N3D ** 2 + 4 * self.N3D) * self.Norb ** 3 * self.Nkz * self.NE * \
             self.NA * self.NB
 
-    def flops(self) -> int:
-        """Algorithmic flops of one component in the reassociated form."""
-        return self.flops_corr() + self.flops_sandwich()
+    def flops(self, antiherm: bool = False) -> int:
+        """Algorithmic flops of one component in the reassociated form; with an
+        anti-Hermitian D~ (D~_ji = -conj(D~_ij)) the tap work halves: three
+        complex filters split into real and imaginary parts (4 real x complex
+        products) plus three imaginary diagonals, 4.5 complex filters in all."""
+        corr = self.flops_corr() // 2 if antiherm else self.flops_corr()
+        return corr + self.flops_sandwich()
 
     def flops_plain(self) -> int:
         """Flops of the plain definition as the oracle evaluates it: per (k, e, q,

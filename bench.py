@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--pi-steps", type=int, default=2,
                     help="timed steps of the phonon self-energy (Eqs. (4)-(5)) at device "
                          "scale, both components (0 = skip)")
+    ap.add_argument("--ablation-steps", type=int, default=1,
+                    help="timed steps of the paper's own final form of Eq. (3) (dH G and "
+                         "dH D precomputed, Norb x Norb Nw x Norb GEMMs on the matrix cores) "
+                         "at device scale, both components (0 = skip)")
     ap.add_argument("--batch", default="fp64,bf16x3",
                     help="precisions of the 48-instance batched run ('' = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=200.0)
@@ -201,6 +205,43 @@ def pi_section(args, torch, sse, prob, seed, DeviceProblem, log):
             "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
                          "kernel": "k_pi_fp64"}}
+
+
+def ablation_section(args, torch, sse, prob, seed, DeviceProblem, log, headline_ms):
+    """The paper's own final form of Eq. (3) on the same problem and inputs
+    (sse_ablation_compute), against the reassociated binary64 kernel of the
+    headline: time to the same Sigma, and its rate in the paper form's own
+    flop count (8 N3D Norb^3 per (k, e, q, w, a, b) plus the dH G products)."""
+    dp = DeviceProblem(prob, seed, ncomp=2)
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw,
+                         ncomp=2)
+    plan = sse.sse_plan(desc, prob.shifts())
+    atoms = 256  # transients of 256 atoms at a time: ~35 GB of workspace
+    ws = torch.empty(sse.ablation_workspace_bytes(desc, atoms), dtype=torch.uint8,
+                     device="cuda")
+    stream = torch.cuda.current_stream()
+    times = []
+    for i in range(args.ablation_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sse.sse_ablation_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        log(f"ablation step {i}: {times[-1] * 1e3:.1f} ms")
+    del dp, ws
+    torch.cuda.empty_cache()
+    med = statistics.median(times)
+    fp = prob.flops_paper_form()
+    tf = fp / (med / 2) / 1e12
+    return {"ms_per_step": round(med * 1e3, 3), "steps": len(times),
+            "time_vs_reassociated": round(med / (headline_ms / 1e3), 2),
+            "flops_per_component": fp,
+            "value_paper_flops": round(2 * fp / med / 1e9, 1), "unit": "GFLOP/s",
+            "value_algorithmic": round(2 * prob.flops() / med / 1e9, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                         "kernel": "k_abl_gemm (+ k_abl_dhg, k_abl_dhd)"}}
 
 
 def aux_section(args, torch, sse, prob, log):
@@ -582,6 +623,9 @@ def main():
         out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, log)
     if args.aux_steps > 0 and not args.only:
         out["aux"] = aux_section(args, torch, sse, prob, log)
+    if args.ablation_steps > 0 and not args.only:
+        out["ablation_paper_form"] = ablation_section(args, torch, sse, prob, seed,
+                                                      DeviceProblem, log, med * 1e3)
     if args.batch:
         out["batch"] = batch_section(args, torch, sse, configs, DeviceProblem, log)
     if args.serving_jobs > 0:

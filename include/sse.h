@@ -263,6 +263,24 @@ sse_status sse_dtilde_submit(sse_plan_t plan, const int32_t *neigh, const void *
  */
 sse_status sse_retarded(sse_plan_t plan, int32_t which, const void *X, void *XR, void *stream);
 
+/*
+ * The same Sigma as sse_compute, evaluated in the paper's own final form of
+ * Eq. (3) (Sec. 4.2): the transients dH.G (M_i[k', e'] = dH[a, b, i] . G[k', e', f])
+ * and dH.D (N_i[q, w] = sum_j Dt[q, w, a, b, i, j] dH[a, b, j]^T) are
+ * precomputed, and for each (a, b, i, k, q) the sum over frequencies is one
+ * Norb x Norb Nw x Norb GEMM of the energy window of M_i with the stacked N_i[q, :]
+ * on the matrix cores (binary64).  8 N3D Norb^3 flops per (k, e, q, w, a, b)
+ * against the 8 N3D^2 Norb^2 of sse_compute: it exists to measure that
+ * difference.  Single-instance SSE_FP64 plans with a general Dt, Norb <= 16;
+ * blocking.  Workspace: 256 bytes plus NB 3 (Nkz NE + Nqz Nw) Norb^2 16 bytes
+ * per atom for at least one atom; atoms are processed in chunks that fit it.
+ * SSE_ERR_UNSUPPORTED outside these limits or when the window needs more LDS
+ * than a compute unit has.
+ */
+sse_status sse_ablation_compute(sse_plan_t plan, const int32_t *neigh, const double *dH,
+                                const void *G, const void *Dt, void *Sigma, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 /* SSE_PENDING while the submission runs, else its final status (the ticket is
  * then released; polling it again gives SSE_ERR_ARG). */
 sse_status sse_poll(uint64_t ticket);

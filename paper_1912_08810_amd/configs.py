@@ -67,6 +67,14 @@ class Problem:
         return 9 * (8 * self.Norb ** 3 + 8 * self.NN) * self.Nkz * self.Nqz * self.NE * \
             self.Nw * self.NA * self.NB
 
+    def flops_paper_form(self) -> int:
+        """Flops of the paper's own final form (Sec. 4.2; its published flop
+        formula divided by the four of {Sigma, Pi} x {<, >}): 8 N3D Norb^3 per
+        (k, e, q, w, a, b) for the Norb x Norb Nw x Norb GEMMs plus 8 N3D Norb^3 per
+        (k, e, a, b) for the dH G products."""
+        pts = self.Nkz * self.NE * self.NA * self.NB
+        return 8 * self.N3D * self.Norb ** 3 * pts * (self.Nqz * self.Nw + 1)
+
     def bytes_compulsory(self, elem_bytes: int = 16) -> int:
         """Read G, D~, dH and neigh once; write Sigma once (one component)."""
         return (2 * self.g_elems() + self.d_elems()) * elem_bytes + \

@@ -1,0 +1,238 @@
+// sse_ablation.hip -- the electron self-energy in the paper's own final form
+// (Sec. 4.2: map fission, redundancy removal, data-layout transformation,
+// multiplication fusion, map expansion and nested-map substitution), for
+// comparison with the reassociated kernel of sse_fp64.hip.  Binary64.
+//
+// With A_i = dH[a, b, i] and the reading dH_ba,j = A_j^T, Eq. (3) regroups as
+//   Sigma[k, e, a] = alpha sum_b sum_i sum_q sum_w M_i[(k - q) mod Nkz, e - s_w] . N_i[q, w]
+//   M_i[k', e'] = A_i . G[k', e', f]             (dH G: one Norb x Norb x Nkz NE Norb GEMM
+//                                                 per (a, b, i), precomputed)
+//   N_i[q, w]   = sum_j Dt[q, w, a, b, i, j] A_j^T   (dH D, precomputed)
+// and for each (a, b, i, k, q) the sum over w is one GEMM of the energy window
+// of M_i rows (Norb x Norb Nw, Toeplitz in (e, w)) with the stacked N_i[q, :]
+// (Norb Nw x Norb): the paper's "N_orb x N_orb N_w x N_orb GEMM".  Here it runs on
+// the matrix cores (v_mfma_f64_16x16x4f64), rows (e, m) of TE energies, columns
+// (n, re/im), K = (w, l, re/im), accumulated over (b, i, q) in the MFMA
+// registers.  The transients M and N live in the caller's workspace, atoms in
+// chunks that fit it.  Per (k, e, q, w, a, b) this form costs 8 N3D Norb^3 flops
+// where the reassociated kernel costs 8 N3D^2 Norb^2 -- the comparison this
+// file exists for.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sse_internal.h"
+
+namespace sse {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// M[al][b][i][k'][e'] = A_i G[k', e', f]: one thread per element (m, l).
+__global__ void k_abl_dhg(AblParams p, int a0, int nat)
+{
+    const int NN = p.NN, No = p.Norb;
+    const int64_t n = (int64_t)nat * p.NB * kN3D * p.Nkz * p.NE * NN;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n)
+        return;
+    const int c = (int)(x % NN);
+    int64_t r = x / NN;
+    const int e = (int)(r % p.NE);
+    r /= p.NE;
+    const int k = (int)(r % p.Nkz);
+    r /= p.Nkz;
+    const int i = (int)(r % kN3D);
+    r /= kN3D;
+    const int b = (int)(r % p.NB);
+    const int a = a0 + (int)(r / p.NB);
+    const int m = c / No, l = c - m * No;
+    const int f = p.neigh[(size_t)a * p.NB + b];
+    double sr = 0.0, si = 0.0;
+    if (f >= 0 && f < p.NA) {
+        const double *A = p.dH + (((size_t)a * p.NB + b) * kN3D + i) * NN + (size_t)m * No;
+        const double2 *G = p.G + (((size_t)k * p.NE + e) * p.NA + f) * NN + l;
+        for (int t = 0; t < No; ++t) {
+            const double2 g = G[(size_t)t * No];
+            sr = fma(A[t], g.x, sr);
+            si = fma(A[t], g.y, si);
+        }
+    }
+    p.M[x] = make_double2(sr, si);
+}
+
+// N[al][b][i][q][w][l][n] = sum_j Dt[q, w, a, b, i, j] A_j[n][l].
+__global__ void k_abl_dhd(AblParams p, int a0, int nat)
+{
+    const int NN = p.NN, No = p.Norb;
+    const int64_t n = (int64_t)nat * p.NB * kN3D * p.Nqz * p.Nw * NN;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n)
+        return;
+    const int c = (int)(x % NN);
+    int64_t r = x / NN;
+    const int w = (int)(r % p.Nw);
+    r /= p.Nw;
+    const int q = (int)(r % p.Nqz);
+    r /= p.Nqz;
+    const int i = (int)(r % kN3D);
+    r /= kN3D;
+    const int b = (int)(r % p.NB);
+    const int a = a0 + (int)(r / p.NB);
+    const int l = c / No, nn = c - l * No;
+    const double2 *D = p.D + ((((size_t)q * p.Nw + w) * p.NA + a) * p.NB + b) * kNF + i * kN3D;
+    const double *A = p.dH + ((size_t)a * p.NB + b) * kN3D * NN + (size_t)nn * No + l;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < kN3D; ++j) {
+        const double h = A[(size_t)j * NN];
+        sr = fma(D[j].x, h, sr);
+        si = fma(D[j].y, h, si);
+    }
+    p.N[x] = make_double2(sr, si);
+}
+
+// One workgroup per (atom of the chunk, k, energy tile): 4 waves, wave t owns
+// rows 16 t .. 16 t + 15 of the TE Norb (<= 64) rows (e, m) and every column
+// tile of the 2 Norb columns (n, re/im).
+__global__ __launch_bounds__(256, 1) void k_abl_gemm(AblParams p, int a0)
+{
+    extern __shared__ double2 lds[];
+    const int NN = p.NN, No = p.Norb, TE = p.TE;
+    const int nrow = p.win_rows;                   // TE + shift spread
+    double2 *win = lds;                            // [nrow][NN]: M_i rows of the window
+    double2 *nb = win + (size_t)nrow * NN;         // [Nw Norb][Norb]: N_i[q, w][l][n]
+    int *rowoff = reinterpret_cast<int *>(nb + (size_t)p.Nw * NN);  // [Nw]: (smax - s_w) NN
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    int64_t L = blockIdx.x;
+    const int et = (int)(L % p.n_etiles);
+    L /= p.n_etiles;
+    const int k = (int)(L % p.Nkz);
+    const int al = (int)(L / p.Nkz);
+    const int a = a0 + al;
+    const int e0 = et * TE;
+    const int te = min(TE, p.NE - e0);
+    for (int w = tid; w < p.Nw; w += 256)
+        rowoff[w] = (p.smax - p.shift[w]) * NN;
+
+    // this lane's A row (e, m) and B column (n, part) within its tiles
+    const int arow = 16 * wave + (lane & 15);
+    const bool arow_ok = arow < TE * No;
+    const int ae = arow_ok ? arow / No : 0, am = arow_ok ? arow - ae * No : 0;
+    const int kq = lane >> 4;            // K' index within an MFMA step: (Kc half, re/im)
+    const int xpart = kq & 1;            // part of M (the A operand) this lane carries
+    const int Kcount = p.Nw * No;        // complex K entries (w, l)
+    v4d acc[pik::kAblNT];
+#pragma unroll
+    for (int t = 0; t < pik::kAblNT; ++t)
+        acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const int ncol = 2 * No;
+
+    for (int b = 0; b < p.NB; ++b) {
+        for (int i = 0; i < kN3D; ++i) {
+            for (int q = 0; q < p.Nqz; ++q) {
+                int kk = k - q;
+                if (kk < 0)
+                    kk += p.Nkz;
+                __syncthreads();
+                const double2 *Mrow = p.M + ((((size_t)al * p.NB + b) * kN3D + i) * p.Nkz + kk) *
+                                                (size_t)p.NE * NN;
+                const int ebase = e0 - p.smax;
+                for (int x = tid; x < nrow * NN; x += 256) {
+                    const int r = x / NN, c = x - r * NN;
+                    const int e = ebase + r;
+                    win[x] = (e >= 0 && e < p.NE) ? Mrow[(size_t)e * NN + c] : make_double2(0.0, 0.0);
+                }
+                const double2 *Nq = p.N + ((((size_t)al * p.NB + b) * kN3D + i) * p.Nqz + q) *
+                                              (size_t)p.Nw * NN;
+                for (int x = tid; x < p.Nw * NN; x += 256)
+                    nb[x] = Nq[x];
+                __syncthreads();
+                // K loop: step s covers complex K entries 2 s and 2 s + 1
+                int Kc = kq >> 1;            // this lane's complex K entry
+                int w = 0, l = Kc;
+                while (l >= No) {
+                    l -= No;
+                    ++w;
+                }
+                for (; Kc - (kq >> 1) < Kcount; Kc += 2) {
+                    const bool kok = Kc < Kcount;
+                    double av = 0.0;
+                    if (kok && arow_ok) {
+                        const double2 m = win[rowoff[w] + ae * NN + am * No + l];
+                        av = xpart ? m.y : m.x;
+                    }
+#pragma unroll
+                    for (int t = 0; t < pik::kAblNT; ++t) {
+                        const int col = 16 * t + (lane & 15);
+                        double bv = 0.0;
+                        if (kok && col < ncol) {
+                            const int n = col >> 1, opart = col & 1;
+                            const double2 v = nb[(size_t)Kc * No + n];
+                            // x re: (re <- N re, im <- N im); x im: (re <- -N im, im <- N re)
+                            bv = xpart ? (opart ? v.x : -v.y) : (opart ? v.y : v.x);
+                        }
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                    }
+                    l += 2;
+                    while (l >= No) {
+                        l -= No;
+                        ++w;
+                    }
+                }
+            }
+        }
+    }
+    // C tiles -> LDS [row][col] (doubles; value r of a lane is row lane / 16 + 4 r of
+    // its tile, column lane % 16), then alpha (re + i im) -> Sigma, coalesced
+    __syncthreads();
+    double *cs = reinterpret_cast<double *>(lds);
+    const int cstride = 16 * pik::kAblNT;
+#pragma unroll
+    for (int t = 0; t < pik::kAblNT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            cs[(16 * wave + (lane >> 4) + 4 * r) * cstride + 16 * t + (lane & 15)] = acc[t][r];
+    __syncthreads();
+    double2 *S = p.Sigma + (((size_t)k * p.NE + e0) * p.NA + a) * NN;
+    for (int x = tid; x < te * NN; x += 256) {
+        const int e = x / NN, c = x - e * NN, m = c / No, n = c - m * No;
+        const double cr = cs[(e * No + m) * cstride + 2 * n], ci = cs[(e * No + m) * cstride + 2 * n + 1];
+        S[(size_t)e * p.NA * NN + c] = make_double2(p.alpha_re * cr - p.alpha_im * ci,
+                                                    p.alpha_re * ci + p.alpha_im * cr);
+    }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t ablation_launch(const AblParams &p, size_t lds_bytes, int chunk_atoms, hipStream_t s)
+{
+    static bool done = false;
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_abl_gemm,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)pik::kLdsBudgetOne);
+        if (e != hipSuccess)
+            return e;
+        done = true;
+    }
+    (void)hipGetLastError();
+    for (int a0 = 0; a0 < p.NA; a0 += chunk_atoms) {
+        const int nat = std::min(chunk_atoms, p.NA - a0);
+        const int64_t nm = (int64_t)nat * p.NB * kN3D * p.Nkz * p.NE * p.NN;
+        const int64_t nn = (int64_t)nat * p.NB * kN3D * p.Nqz * p.Nw * p.NN;
+        hipLaunchKernelGGL(k_abl_dhg, dim3(nblk(nm)), dim3(256), 0, s, p, a0, nat);
+        hipLaunchKernelGGL(k_abl_dhd, dim3(nblk(nn)), dim3(256), 0, s, p, a0, nat);
+        const int64_t nwg = (int64_t)nat * p.Nkz * p.n_etiles;
+        hipLaunchKernelGGL(k_abl_gemm, dim3((unsigned)nwg), dim3(256), lds_bytes, s, p, a0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace sse

@@ -228,6 +228,29 @@ struct PiParams {
 };
 
 PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw);
+
+// The paper's own final form of Eq. (3) (sse_ablation.hip): transients
+// M = dH G [chunk atoms][NB][3][Nkz][NE][Norb][Norb] and N = dH D
+// [chunk atoms][NB][3][Nqz][Nw][Norb][Norb] in the workspace, then the
+// Norb x Norb Nw x Norb GEMMs on the matrix cores.
+namespace pik {
+constexpr int kAblNT = 2;       // column tiles of 16: 2 Norb <= 32
+constexpr int kAblRows = 64;    // rows (e, m) per workgroup: 4 waves x 16
+}  // namespace pik
+struct AblParams {
+    const int32_t *neigh;
+    const double *dH;
+    const double2 *G;
+    const double2 *D;
+    double2 *Sigma;
+    double2 *M;
+    double2 *N;
+    int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
+    int32_t TE, n_etiles, smax, win_rows;
+    double alpha_re, alpha_im;
+    int32_t shift[kMaxTaps];
+};
+hipError_t ablation_launch(const AblParams &p, size_t lds_bytes, int chunk_atoms, hipStream_t s);
 hipError_t pi_launch(const PiParams &p, size_t lds_bytes, hipStream_t s);
 
 // Sampled binary64 check of a complex64 result (sse_check.hip).

@@ -997,6 +997,81 @@ sse_status sse_retarded(sse_plan_t plan, int32_t which, const void *X, void *XR,
     return SSE_OK;
 }
 
+sse_status sse_ablation_compute(sse_plan_t plan, const int32_t *neigh, const double *dH,
+                                const void *G, const void *Dt, void *Sigma, void *workspace,
+                                size_t workspace_bytes, void *stream)
+{
+    if (!plan || !neigh || !dH || !G || !Dt || !Sigma || !workspace)
+        return fail(SSE_ERR_ARG, "sse_ablation_compute: NULL argument");
+    if (plan->batch || plan->inst.size() != 1)
+        return fail(SSE_ERR_ARG, "sse_ablation_compute: needs a single-instance plan");
+    const Instance &I = plan->inst[0];
+    const sse_desc &d = I.d;
+    if (d.prec != SSE_FP64 || d.dt_antiherm)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_ablation_compute: SSE_FP64 with a general Dt only");
+    if (2 * d.Norb > 16 * pik::kAblNT)
+        return fail(SSE_ERR_UNSUPPORTED, "sse_ablation_compute: Norb <= %d", 8 * pik::kAblNT);
+    const size_t NN = (size_t)d.Norb * d.Norb;
+    AblParams p{};
+    p.NA = d.NA;
+    p.NB = d.NB;
+    p.Norb = d.Norb;
+    p.NN = (int)NN;
+    p.Nkz = d.Nkz;
+    p.Nqz = d.Nqz;
+    p.NE = d.NE;
+    p.Nw = d.Nw;
+    p.TE = std::max(1, pik::kAblRows / d.Norb);
+    p.n_etiles = (d.NE + p.TE - 1) / p.TE;
+    int smin = I.shift[0], smax = I.shift[0];
+    for (int w = 0; w < d.Nw; ++w) {
+        smin = std::min(smin, I.shift[w]);
+        smax = std::max(smax, I.shift[w]);
+        p.shift[w] = I.shift[w];
+    }
+    p.smax = smax;
+    p.win_rows = p.TE + smax - smin;
+    p.alpha_re = d.alpha_re;
+    p.alpha_im = d.alpha_im;
+    const size_t lds = std::max(((size_t)p.win_rows * NN + (size_t)d.Nw * NN) * 16 + 4 * d.Nw,
+                                (size_t)pik::kAblRows * 16 * pik::kAblNT * 8);
+    if (lds > pik::kLdsBudgetOne)
+        return fail(SSE_ERR_UNSUPPORTED,
+                    "sse_ablation_compute: window and N_i blocks need %zu bytes of LDS", lds);
+    const size_t per_atom = (size_t)d.NB * kN3D * ((size_t)d.Nkz * d.NE + (size_t)d.Nqz * d.Nw) *
+                            NN * 16;
+    if (workspace_bytes < kStatusBytes + per_atom)
+        return fail(SSE_ERR_ARG, "sse_ablation_compute: workspace of at least %zu bytes needed",
+                    kStatusBytes + per_atom);
+    const int chunk = (int)std::min<size_t>(d.NA, (workspace_bytes - kStatusBytes) / per_atom);
+    p.M = (double2 *)((char *)workspace + kStatusBytes);
+    p.N = p.M + (size_t)chunk * d.NB * kN3D * d.Nkz * d.NE * NN;
+    p.neigh = neigh;
+    p.dH = dH;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *dstatus = (uint32_t *)workspace;
+    hipError_t e = launch_clear_status(dstatus, s);
+    if (e == hipSuccess)
+        e = launch_validate_neigh(neigh, (int64_t)d.NA * d.NB, d.NA, dstatus, s);
+    const size_t g_elems = (size_t)d.Nkz * d.NE * d.NA * NN;
+    const size_t d_elems = (size_t)d.Nqz * d.Nw * d.NA * d.NB * kNF;
+    for (int c = 0; c < d.ncomp && e == hipSuccess; ++c) {
+        p.G = (const double2 *)G + c * g_elems;
+        p.D = (const double2 *)Dt + c * d_elems;
+        p.Sigma = (double2 *)Sigma + c * g_elems;
+        e = ablation_launch(p, lds, chunk, s);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "ablation kernel launch");
+    uint32_t hs = 0xffffffffu;
+    e = hipMemcpyAsync(&hs, dstatus, sizeof hs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "sse_ablation_compute: waiting for the computation");
+    return status_from_word(hs);
+}
+
 sse_status sse_compute(sse_plan_t plan, const int32_t *neigh, const double *dH, const void *G,
                        const void *Dt, void *Sigma, void *workspace, size_t workspace_bytes,
                        void *stream)

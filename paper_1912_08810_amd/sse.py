@@ -74,6 +74,7 @@ def _load():
     L.sse_pi_compute.argtypes = [vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
     L.sse_dtilde_submit.argtypes = [vp, vp, vp, vp, vp, c.c_size_t, vp, c.POINTER(c.c_uint64)]
     L.sse_retarded.argtypes = [vp, c.c_int32, vp, vp, vp]
+    L.sse_ablation_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp, c.c_size_t, vp]
     L.sse_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_size_t, vp,
                              c.POINTER(c.c_uint64)]
     L.sse_check_submit.argtypes = [vp, c.POINTER(sse_args), vp, c.c_int32, c.c_double, vp, vp,
@@ -85,7 +86,7 @@ def _load():
     L.sse_last_error.restype = c.c_char_p
     for f in (L.sse_plan, L.sse_plan_batch, L.sse_compute, L.sse_compute_noalloc, L.sse_submit,
               L.sse_poll, L.sse_wait, L.sse_check_submit, L.sse_pi_submit, L.sse_pi_compute,
-              L.sse_dtilde_submit, L.sse_retarded):
+              L.sse_dtilde_submit, L.sse_retarded, L.sse_ablation_compute):
         f.restype = c.c_int
     return L
 
@@ -93,7 +94,8 @@ def _load():
 lib = _load()
 
 # Every symbol include/sse.h declares (checked by the CPU test of the library).
-EXPORTS = ["sse_check_submit", "sse_compute", "sse_compute_noalloc", "sse_dtilde_submit",
+EXPORTS = ["sse_ablation_compute", "sse_check_submit", "sse_compute", "sse_compute_noalloc",
+           "sse_dtilde_submit",
            "sse_last_error", "sse_pi_compute", "sse_pi_submit", "sse_plan", "sse_plan_batch",
            "sse_plan_destroy", "sse_poll", "sse_retarded", "sse_submit", "sse_wait"]
 NOALLOC_SCRATCH_BYTES = 32 << 20  # SSE_NOALLOC_SCRATCH_BYTES
@@ -227,6 +229,20 @@ def sse_retarded(plan: Plan, which: int, X, XR, stream=None, check=True) -> int:
     """XR = (X[1] - X[0]) / 2; which 0 = Sigma, 1 = Pi."""
     st = lib.sse_retarded(plan.handle, which, _ptr(X), _ptr(XR), _stream(stream))
     return _check(st, "sse_retarded") if check else st
+
+
+def ablation_workspace_bytes(desc, atoms: int) -> int:
+    """Workspace of sse_ablation_compute holding the transients of `atoms` atoms."""
+    per = desc.NB * 3 * (desc.Nkz * desc.NE + desc.Nqz * desc.Nw) * desc.Norb ** 2 * 16
+    return 256 + per * atoms
+
+
+def sse_ablation_compute(plan: Plan, neigh, dH, G, Dt, Sigma, workspace, stream=None,
+                         check=True) -> int:
+    nbytes = workspace.numel() * workspace.element_size()
+    st = lib.sse_ablation_compute(plan.handle, _ptr(neigh), _ptr(dH), _ptr(G), _ptr(Dt),
+                                  _ptr(Sigma), _ptr(workspace), nbytes, _stream(stream))
+    return _check(st, "sse_ablation_compute") if check else st
 
 
 def _args(items):

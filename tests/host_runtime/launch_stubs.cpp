@@ -114,3 +114,6 @@ hipError_t dtilde_launch(const void *, void *, const int32_t *, int32_t *, uint3
 }
 hipError_t retarded_launch(const void *, void *, int64_t, bool, hipStream_t) { return hipGetLastError(); }
 }  // namespace sse
+namespace sse {
+hipError_t ablation_launch(const AblParams &, size_t, int, hipStream_t) { return hipGetLastError(); }
+}  // namespace sse

@@ -42,7 +42,8 @@ def parse():
                     help="timed steps of the D -> D~ and retarded passes at device scale "
                          "(0 = skip)")
     ap.add_argument("--only", default="",
-                    help="time only this form (fp64, fp32 or bf16x3), e.g. for profiling")
+                    help="time only this part, e.g. for profiling: a precision form (fp64, "
+                         "fp32, bf16x3, fp64c64, fp64ah) or a section (pi, ablation, aux)")
     ap.add_argument("--pi-steps", type=int, default=2,
                     help="timed steps of the phonon self-energy (Eqs. (4)-(5)) at device "
                          "scale, both components (0 = skip)")
@@ -535,6 +536,21 @@ def main():
         progress(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
         torch.cuda.empty_cache()
+    if args.only in ("pi", "ablation", "aux"):
+        # one section alone (profiling runs); the ablation compares with the
+        # headline, so that case times one binary64 step first
+        out = {}
+        if args.only == "pi":
+            out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, progress)
+        elif args.only == "aux":
+            out["aux"] = aux_section(args, torch, sse, prob, progress)
+        else:
+            ht, _ = time_form(sse.FP64, False, False)
+            out["ablation_paper_form"] = ablation_section(args, torch, sse, prob, seed,
+                                                          DeviceProblem, progress,
+                                                          statistics.median(ht) * 1e3)
+        print(json.dumps(out), flush=True)
+        return
     forms = [f for f in args.forms.split(",") if f]
     if args.only:
         forms = [args.only] if args.only != "fp64" else []

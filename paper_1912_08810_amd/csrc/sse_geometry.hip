@@ -116,14 +116,15 @@ size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int No
     return b;
 }
 
-// Tap chunks of the phonon kernel (sse_pi.hip): taps sorted by increasing
-// shift, cut where a chunk would exceed the workgroup's tap groups or its ring
-// of rows would not fit the LDS budget.
-PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw)
+// Geometry of the phonon kernel (sse_pi.hip): the most neighbours per
+// workgroup (up to 4) whose sandwich buffers leave room for a ring of the
+// taps' rows, then the taps, sorted by increasing shift, cut into chunks of at
+// most 32 whose ring fits.  LDS per workgroup: ring R rows, per neighbour 13
+// complex128 blocks (Zt 9, U 3, Y 1) and 3 binary64 dH blocks.
+PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
 {
     PiGeom gm{};
-    const int NN = Norb * Norb;
-    const int kNT = pik::kNT;
+    const size_t NN = (size_t)Norb * Norb;
     std::vector<int> order(Nw);
     for (int w = 0; w < Nw; ++w)
         order[w] = w;
@@ -133,39 +134,37 @@ PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw)
         gm.tw[t] = order[t];
         gm.ts[t] = w_shift[order[t]];
     }
-    // LDS per workgroup: ring R rows + Zt (9) + U (3) + Y (1) blocks of complex128,
-    // dH (3 blocks of binary64); two workgroups per CU if the taps fit, else one.
-    const size_t fixed = (size_t)NN * 16 * 13 + (size_t)NN * 8 * 3;
-    const size_t per_row = (size_t)NN * 16;
-    int rmax = (int)(((size_t)pik::kLdsBudget - std::min(fixed, (size_t)pik::kLdsBudget)) / per_row);
-    gm.lds_budget = pik::kLdsBudget;
-    if (rmax < std::min(gm.ts[Nw - 1] - gm.ts[0] + 1, 16)) {
-        rmax = (int)(((size_t)pik::kLdsBudgetOne - std::min(fixed, (size_t)pik::kLdsBudgetOne)) /
-                     per_row);
-        gm.lds_budget = pik::kLdsBudgetOne;
+    const size_t per_nb = NN * (13 * 16 + 3 * 8), per_row = NN * 16;
+    const size_t budget = pik::kLdsBudgetOne;
+    const int want_rows = std::min(gm.ts[Nw - 1] - gm.ts[0] + 1, 8);
+    int rmax = 0;
+    for (gm.nbw = std::min(NB, pik::kMaxNbw); gm.nbw >= 1; --gm.nbw) {
+        const size_t fixed = per_nb * gm.nbw;
+        rmax = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
+        if (rmax >= want_rows || gm.nbw == 1)
+            break;
     }
     gm.R = 0;
     gm.nchunk = 0;
+    int maxtaps = 0;
     int t = 0;
-    while (t < Nw) {
+    while (t < Nw && rmax >= 1) {
         int e = t + 1;
-        while (e < Nw && e - t < pik::kMaxGroups * kNT && gm.ts[e] - gm.ts[t] + 1 <= rmax)
+        while (e < Nw && e - t < pik::kMaxChunkTaps && gm.ts[e] - gm.ts[t] + 1 <= rmax)
             ++e;
         gm.cb[gm.nchunk] = t;
-        int groups = (e - t + kNT - 1) / kNT;
-        int pow2 = 1;
-        while (pow2 < groups)
-            pow2 <<= 1;
-        gm.cg[gm.nchunk] = pow2;
         gm.R = std::max(gm.R, gm.ts[e - 1] - gm.ts[t] + 1);
+        maxtaps = std::max(maxtaps, e - t);
         ++gm.nchunk;
         t = e;
     }
     gm.cb[gm.nchunk] = Nw;
-    gm.lds_bytes = (size_t)gm.R * per_row + fixed;
-    // the final reduction reuses the ring for 4 waves x 9 x kNT complex values
-    gm.lds_bytes = std::max(gm.lds_bytes, (size_t)4 * kNF * kNT * 16);
-    gm.ok = rmax >= 1;
+    gm.mtiles = maxtaps <= 16 ? 1 : 2;
+    const int ntn = (gm.nbw * 9 * 2 + 15) / 16;
+    // the final reduction reuses LDS for half the waves' accumulator tiles
+    gm.lds_bytes = std::max((size_t)gm.R * per_row + per_nb * gm.nbw,
+                            (size_t)(pik::kWaves / 2) * 16 * gm.mtiles * 16 * ntn * 8);
+    gm.ok = rmax >= 1 && gm.lds_bytes <= budget;
     return gm;
 }
 

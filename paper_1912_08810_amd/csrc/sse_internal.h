@@ -185,29 +185,31 @@ struct Fp64Params {
 void fill_tap_pairs(Fp64Params &p);
 
 
-// Phonon self-energy kernel (sse_pi.hip): 256 threads, each holding the 9 (i, j)
-// accumulators of kNT taps; up to kMaxGroups tap groups per workgroup.
+// Phonon self-energy kernel (sse_pi.hip): 512 threads (8 waves, two per SIMD)
+// per workgroup, one workgroup per CU; a chunk holds at most kMaxChunkTaps taps
+// (two row tiles of the matrix cores) and a workgroup at most kMaxNbw
+// neighbours (18 nbw <= 80 columns).
 namespace pik {
-constexpr int kBlock = 256;
-constexpr int kNT = 4;
-constexpr int kMaxGroups = 8;
-constexpr size_t kLdsBudget = 78 * 1024;     // two workgroups per CU
-constexpr size_t kLdsBudgetOne = 156 * 1024; // one workgroup per CU (large Norb)
+constexpr int kBlock = 512;
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxChunkTaps = 32;
+constexpr int kMaxNbw = 4;
+constexpr size_t kLdsBudgetOne = 156 * 1024;
 constexpr int kMaxNorb = 16;                 // a G block row fits one load per thread
 }  // namespace pik
 
 // Tap chunks of the phonon kernel: taps sorted by increasing shift (tap t uses
-// frequency tw[t], shift ts[t]); chunk c covers taps [cb[c], cb[c+1]) with
-// cg[c] tap groups (a power of two) and a ring of at most R rows.
+// frequency tw[t], shift ts[t]); chunk c covers taps [cb[c], cb[c+1]) and needs a
+// ring of at most R rows.  nbw neighbours per workgroup, mtiles row tiles.
 struct PiGeom {
     int32_t nchunk;
     int32_t R;
+    int32_t nbw;
+    int32_t mtiles;
     int32_t cb[kMaxTaps + 1];
-    int32_t cg[kMaxTaps];
     int32_t tw[kMaxTaps];
     int32_t ts[kMaxTaps];
     size_t lds_bytes;
-    size_t lds_budget;
     bool ok;
 };
 
@@ -218,16 +220,15 @@ struct PiParams {
     const int32_t *neigh;
     double2 *Pi;       // [Nqz, Nw, NA, NB + 1, 3, 3]
     int32_t NA, NB, Norb, NN, Nkz, Nqz, NE, Nw;
-    int32_t nchunk, R;
+    int32_t nchunk, R, nbw, nbgroups, mtiles;
     int32_t cb[kMaxTaps + 1];
-    int32_t cg[kMaxTaps];
     int32_t tw[kMaxTaps];
     int32_t ts[kMaxTaps];
-    int64_t n_wg;      // NA * NB * Nqz * nchunk
+    int64_t n_wg;      // NA * Nqz * nbgroups * nchunk
     double beta_re, beta_im;
 };
 
-PiGeom pi_geometry(int Norb, const int32_t *w_shift, int Nw);
+PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw);
 
 // The paper's own final form of Eq. (3) (sse_ablation.hip): transients
 // M = dH G [chunk atoms][NB][3][Nkz][NE][Norb][Norb] and N = dH D

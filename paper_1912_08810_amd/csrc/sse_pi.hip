@@ -12,25 +12,27 @@
 // Z_ij = dH_j . Y . dH_i^T, so that
 //   P_ij[q, w] = sum_k sum_e sum_{n,p} X[k + q, e + s_w][n][p] * Zt_ij[k, e][n][p],
 //   Zt_ij[n][p] = Z_ij[p][n] = sum_m dH_i[n][m] (dH_j . Y)[p][m]:
-// the two Norb x Norb products run once per (k, e) of the workgroup (not once
-// per frequency), and each frequency costs one complex multiply-add per orbital
-// pair and (i, j) -- the (q, w) correlation the paper's Sec. 4.2 rewrites into
-// one GEMM, here without any Norb x Norb product inside it.
+// the two Norb x Norb products run once per (k, e) of a workgroup (not once per
+// frequency), and each frequency costs one complex multiply-add per orbital pair
+// and (i, j) -- the (q, w) correlation that Sec. 4.2 turns into one GEMM, here
+// without any Norb x Norb product inside it.
 //
-// Work decomposition: one 256-thread workgroup per (atom a, neighbour slot b,
-// momentum q, tap chunk).  It walks k and then e (one energy per step); per step
-// the neighbour's block Y[k, e, f] is staged and sandwiched into Zt (two rounds
-// of Norb-long dot products through LDS), and atom a's rows X[k + q, e + s] for
-// the chunk's shifts are kept in a ring of R = s_hi - s_lo + 1 rows in LDS that
-// advances one row per step (rows outside the energy grid are zero).  Thread
-// (g, p) owns the 9 x kNT accumulators of (i, j) and the 4 taps of tap group g
-// and sums them over the orbital pairs p, p + P, ... of every step; the P
-// partial sums of a group are reduced once at the end, in a fixed order.  The
-// next step's two rows are loaded into registers while a step's taps run.
+// The correlation is a GEMM on the matrix cores (v_mfma_f64_16x16x4f64):
+// rows = the frequencies (taps) of a chunk, columns = (b, i, j, re/im) for the
+// nbw neighbours of the workgroup, K = (orbital pair, re/im of X), summed over
+// every (k, e).  A = X rows, read from a ring of atom a's rows in LDS (a tap is
+// an offset into it); B = Zt in LDS, the complex product folded into the
+// operand's sign and part.  One workgroup (8 waves) per (atom a, momentum q,
+// group of nbw neighbours, tap chunk) walks k, then e one energy per step: per
+// step the nbw neighbours' blocks Y[k, e, f] are staged and sandwiched into Zt
+// on the vector units (two rounds of Norb-long dot products through LDS), the
+// ring advances one row, and the eight waves split the step's K range, each
+// holding every output tile in its matrix-core accumulators; the eight partial
+// sums are added in a fixed order at the end.  The next step's rows load into
+// registers while a step's MFMAs run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <vector>
 
 #include "sse_internal.h"
 
@@ -39,21 +41,13 @@ namespace sse {
 namespace {
 
 constexpr int kBlock = pik::kBlock;
-constexpr int kNT = pik::kNT;
-
-__device__ __forceinline__ void cmac(double &accr, double &acci, double ar, double ai, double br,
-                                     double bi)
-{
-    accr = fma(ar, br, accr);
-    accr = fma(-ai, bi, accr);
-    acci = fma(ar, bi, acci);
-    acci = fma(ai, br, acci);
-}
+constexpr int kYP = 2;  // staged Y elements per thread and step (nbw NN <= 1024)
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Logical workgroup of physical workgroup `bid`: workgroups are dispatched
 // round-robin over the 8 XCDs, so give each XCD a contiguous range of logical
-// indices (the b, q and chunk workgroups of one atom, which read the same rows
-// of its G, share an L2).
+// indices (the q, neighbour-group and chunk workgroups of one atom, which read
+// the same rows of its G, share an L2).
 __device__ __forceinline__ int64_t xcd_logical(int64_t bid, int64_t n)
 {
     const int64_t per = n >> 3, rem = n & 7;
@@ -67,222 +61,296 @@ __device__ __forceinline__ int ring_slot(int row, int R)
     return m < 0 ? m + R : m;
 }
 
-// First sandwich round: U_j[p][m] = sum_r dH_j[p][r] Y[r][m], j < 3.
+// First sandwich round: U[b][j][p][m] = sum_r dH_bj[p][r] Y_b[r][m]; a thread
+// takes one (b, p, m) and all three j, sharing the loads of Y's column.
 __device__ __forceinline__ void sandwich_first(const double *dHs, const double2 *Ys, double2 *Us,
-                                               int NN, int No, int tid)
+                                               int nbw, int NN, int No, int tid)
 {
 #pragma unroll 1
-    for (int o = tid; o < 3 * NN; o += kBlock) {
-        const int j = o / NN, rem = o - j * NN, r0 = rem / No, m = rem - r0 * No;
-        double ur = 0.0, ui = 0.0;
+    for (int o = tid; o < nbw * NN; o += kBlock) {
+        const int b = o / NN, rem = o - b * NN, r0 = rem / No, m = rem - r0 * No;
+        const double *h = dHs + (size_t)b * 3 * NN + r0 * No;
+        const double2 *y = Ys + (size_t)b * NN + m;
+        double ur[3] = {0.0, 0.0, 0.0}, ui[3] = {0.0, 0.0, 0.0};
+#pragma unroll 2
         for (int r = 0; r < No; ++r) {
-            const double h = dHs[j * NN + r0 * No + r];
-            const double2 y = Ys[r * No + m];
-            ur = fma(h, y.x, ur);
-            ui = fma(h, y.y, ui);
+            const double2 v = y[r * No];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double hj = h[j * NN + r];
+                ur[j] = fma(hj, v.x, ur[j]);
+                ui[j] = fma(hj, v.y, ui[j]);
+            }
         }
-        Us[o] = make_double2(ur, ui);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Us[((size_t)b * 3 + j) * NN + rem] = make_double2(ur[j], ui[j]);
     }
 }
 
-// Second round: Zt_ij[n][p] = sum_m dH_i[n][m] U_j[p][m] (= (dH_j Y dH_i^T)[p][n]).
-__device__ __forceinline__ void sandwich_second(const double *dHs, const double2 *Us, double2 *Zs,
-                                                int NN, int No, int tid)
+// Second round: Zb[c][b 9 + 3 i + j] = Zt_bij[n][p] = sum_m dH_bi[n][m] U[b][j][p][m],
+// c = n Norb + p (the orbital pair of X it multiplies); a thread takes one
+// (c, b) and all nine (i, j), sharing the loads of the three dH rows and the
+// three U rows.
+__device__ __forceinline__ void sandwich_second(const double *dHs, const double2 *Us, double2 *Zb,
+                                                int nbw, int NN, int No, int tid)
 {
+    const int ncol = nbw * kNF;
 #pragma unroll 1
-    for (int o = tid; o < kNF * NN; o += kBlock) {
-        const int ij = o / NN, rem = o - ij * NN, n = rem / No, r0 = rem - n * No;
-        const int i = ij / 3, j = ij - 3 * i;
-        double zr = 0.0, zi = 0.0;
+    for (int o = tid; o < NN * nbw; o += kBlock) {
+        const int c = o / nbw, b = o - c * nbw;
+        const int n = c / No, r0 = c - n * No;
+        const double *h = dHs + (size_t)b * 3 * NN + n * No;
+        const double2 *u = Us + (size_t)b * 3 * NN + r0 * No;
+        double zr[kNF], zi[kNF];
+#pragma unroll
+        for (int x = 0; x < kNF; ++x)
+            zr[x] = zi[x] = 0.0;
+#pragma unroll 2
         for (int m = 0; m < No; ++m) {
-            const double h = dHs[i * NN + n * No + m];
-            const double2 u = Us[j * NN + r0 * No + m];
-            zr = fma(h, u.x, zr);
-            zi = fma(h, u.y, zi);
+            double hi[3];
+            double2 uj[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                hi[t] = h[t * NN + m];
+                uj[t] = u[t * NN + m];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    zr[3 * i + j] = fma(hi[i], uj[j].x, zr[3 * i + j]);
+                    zi[3 * i + j] = fma(hi[i], uj[j].y, zi[3 * i + j]);
+                }
         }
-        Zs[o] = make_double2(zr, zi);
+        double2 *out = Zb + (size_t)c * ncol + b * kNF;
+#pragma unroll
+        for (int x = 0; x < kNF; ++x)
+            out[x] = make_double2(zr[x], zi[x]);
     }
 }
 
-__global__ __launch_bounds__(kBlock, 1) void k_pi_fp64(const PiParams p)
+template <int MT, int NTN>
+__global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
 {
     extern __shared__ double2 lds[];
-    const int NN = p.NN, No = p.Norb, R = p.R;
-    double2 *ring = lds;                 // [R][NN]
-    double2 *Zs = ring + (size_t)R * NN; // [9][NN]: Zt_ij[n][p] at ij * NN + n * No + p
-    double2 *Us = Zs + 9 * NN;           // [3][NN]: (dH_j . Y)[p][m]
-    double2 *Ys = Us + 3 * NN;           // [NN]
-    double *dHs = reinterpret_cast<double *>(Ys + NN);  // [3][NN]
-    const int tid = threadIdx.x;
+    const int NN = p.NN, No = p.Norb, R = p.R, nbw = p.nbw, ncol = nbw * kNF;
+    double2 *ring = lds;                          // [R][NN]
+    double2 *Zb = ring + (size_t)R * NN;          // [NN][nbw 9]
+    double2 *Us = Zb + (size_t)NN * ncol;         // [nbw 3][NN]
+    double2 *Ys = Us + (size_t)nbw * 3 * NN;      // [nbw][NN]
+    double *dHs = reinterpret_cast<double *>(Ys + (size_t)nbw * NN);  // [nbw 3][NN]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     int64_t L = xcd_logical(blockIdx.x, p.n_wg);
     const int chunk = (int)(L % p.nchunk);
     L /= p.nchunk;
+    const int bg = (int)(L % p.nbgroups);
+    L /= p.nbgroups;
     const int q = (int)(L % p.Nqz);
-    L /= p.Nqz;
-    const int b = (int)(L % p.NB);
-    const int a = (int)(L / p.NB);
-    const int f = p.neigh[(size_t)a * p.NB + b];
+    const int a = (int)(L / p.Nqz);
+    const int b0 = bg * nbw;
+    const int nbv = min(nbw, p.NB - b0);          // neighbours of this workgroup
     const int t0 = p.cb[chunk], t1 = p.cb[chunk + 1];
     const int s_lo = p.ts[t0], s_hi = p.ts[t1 - 1];
-    const int ngroups = p.cg[chunk];
-    const int P = kBlock / ngroups;
-    const int g = tid / P, pp = tid % P;
-    const size_t out_a = (size_t)a * (p.NB + 1) + b;  // output block (.., a, b) per (q, w)
-    const size_t qw_stride = (size_t)p.NA * (p.NB + 1) * kNF;
 
-    if (f < 0 || f >= p.NA) {
-        // reported by the neighbour check; the block is left zero
-        for (int t = t0 + tid; t < t1; t += kBlock)
-            for (int ij = 0; ij < kNF; ++ij)
-                p.Pi[((size_t)q * p.Nw + p.tw[t]) * qw_stride + out_a * kNF + ij] =
-                    make_double2(0.0, 0.0);
-        return;
+    for (int x = tid; x < nbw * 3 * NN; x += kBlock) {
+        const int b = x / (3 * NN);
+        dHs[x] = b < nbv ? p.dH[((size_t)a * p.NB + b0) * 3 * NN + x] : 0.0;
     }
 
-    for (int x = tid; x < 3 * NN; x += kBlock)
-        dHs[x] = p.dH[((size_t)a * p.NB + b) * 3 * NN + x];
-
-    // this thread's taps; unused slots repeat the chunk's first shift
-    int su[kNT];
-    bool valid[kNT];
+    // per lane: its tap row in each row tile, its K' slot, its columns
+    const int kq = lane >> 4, xpart = kq & 1, chalf = kq >> 1;
+    int tap_s[MT];
+    bool tap_ok[MT];
 #pragma unroll
-    for (int u = 0; u < kNT; ++u) {
-        const int t = t0 + g * kNT + u;
-        valid[u] = g < ngroups && t < t1;
-        su[u] = valid[u] ? p.ts[t] : s_lo;
+    for (int mt = 0; mt < MT; ++mt) {
+        const int t = t0 + 16 * mt + (lane & 15);
+        tap_ok[mt] = t < t1;
+        tap_s[mt] = tap_ok[mt] ? p.ts[t] : s_lo;
     }
-    double accr[kNF][kNT], acci[kNF][kNT];
+    int bcol[NTN];     // column (b, i, j) of this lane in each column tile, -1 = padding
+    int bcomp[NTN];    // component of Zt it reads: re (0) or im (1)
+    double bsign[NTN];
 #pragma unroll
-    for (int ij = 0; ij < kNF; ++ij)
+    for (int nt = 0; nt < NTN; ++nt) {
+        const int col = 16 * nt + (lane & 15), bij = col >> 1, op = col & 1;
+        const bool ok = bij < nbv * kNF;
+        bcol[nt] = ok ? bij : -1;
+        // x re: (out re <- Z re, out im <- Z im); x im: (out re <- -Z im, out im <- Z re)
+        bcomp[nt] = xpart ^ op;
+        bsign[nt] = (xpart && !op) ? -1.0 : 1.0;
+    }
+    v4d acc[MT][NTN];
 #pragma unroll
-        for (int u = 0; u < kNT; ++u)
-            accr[ij][u] = acci[ij][u] = 0.0;
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTN; ++nt)
+            acc[mt][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
 
     const size_t row_stride = (size_t)p.NA * NN;  // one energy step of G
     const double2 zero = make_double2(0.0, 0.0);
+    const int nks = (NN + 1) >> 1;                // MFMA steps (two orbital pairs each) per energy
+    const int nyel = nbw * NN;                    // staged Y elements per step
 
     for (int k = 0; k < p.Nkz; ++k) {
         const int kx = (k + q) % p.Nkz;
         const double2 *Xk = p.X + ((size_t)kx * p.NE * p.NA + a) * NN;
-        const double2 *Yk = p.Y + ((size_t)k * p.NE * p.NA + f) * NN;
+        const double2 *Yk = p.Y + (size_t)k * p.NE * row_stride;
+        // Y element x of energy e (neighbour x / NN of the group, pair x % NN);
+        // ok = false for a padding slot or an invalid neighbour (then zero)
+        auto yaddr = [&](int x, int e, bool &ok) -> const double2 * {
+            const int b = x / NN, c = x - b * NN;
+            const int f = b < nbv ? p.neigh[(size_t)a * p.NB + b0 + b] : -1;
+            ok = f >= 0 && f < p.NA;
+            return Yk + (size_t)e * row_stride + (size_t)(ok ? f : 0) * NN + c;
+        };
         __syncthreads();  // the previous k's last step is done with the ring, Us and Ys
-        // ring rows s_lo .. s_hi - 1 (step 0's rows but its top one); Y[k, 0, f]
+        // ring rows s_lo .. s_hi - 1 (step 0's rows but its top one); Y of step 0
         for (int x = tid; x < (s_hi - s_lo) * NN; x += kBlock) {
             const int row = s_lo + x / NN, c = x % NN;
             ring[ring_slot(row, R) * NN + c] =
                 (row >= 0 && row < p.NE) ? Xk[(size_t)row * row_stride + c] : zero;
         }
-        double2 yv = zero, xv = zero;  // rows in flight: Y of a later step, the ring's next top row
-        if (tid < NN) {
-            Ys[tid] = Yk[tid];
-            if (s_hi >= 0 && s_hi < p.NE)
-                xv = Xk[(size_t)s_hi * row_stride + tid];
-            if (1 < p.NE)
-                yv = Yk[row_stride + tid];
+        double2 yv[kYP], xv = zero;  // rows in flight: Y of a later step, the ring's next top row
+#pragma unroll
+        for (int u = 0; u < kYP; ++u) {
+            const int x = tid + u * kBlock;
+            yv[u] = zero;
+            if (x < nyel) {
+                bool ok;
+                const double2 *src = yaddr(x, 0, ok);
+                Ys[x] = ok ? *src : zero;
+                if (ok && 1 < p.NE)
+                    yv[u] = src[row_stride];
+            }
         }
+        if (tid < NN && s_hi >= 0 && s_hi < p.NE)
+            xv = Xk[(size_t)s_hi * row_stride + tid];
         __syncthreads();
-        sandwich_first(dHs, Ys, Us, NN, No, tid);
+        sandwich_first(dHs, Ys, Us, nbw, NN, No, tid);
         __syncthreads();
         for (int es = 0;; ++es) {
             // ---- phase B: second sandwich round of step es; the ring's top row
-            // for step es and Y of step es + 1 go to LDS; the next two rows load
+            // for step es and Y of step es + 1 go to LDS; the next rows load
             if (es < p.NE) {
-                sandwich_second(dHs, Us, Zs, NN, No, tid);
+                sandwich_second(dHs, Us, Zb, nbw, NN, No, tid);
                 if (tid < NN) {
                     ring[ring_slot(es + s_hi, R) * NN + tid] = xv;
-                    if (es + 1 < p.NE)
-                        Ys[tid] = yv;
                     xv = zero;
-                    yv = zero;
                     const int row = es + 1 + s_hi;
                     if (row >= 0 && row < p.NE)
                         xv = Xk[(size_t)row * row_stride + tid];
-                    if (es + 2 < p.NE)
-                        yv = Yk[(size_t)(es + 2) * row_stride + tid];
+                }
+#pragma unroll
+                for (int u = 0; u < kYP; ++u) {
+                    const int x = tid + u * kBlock;
+                    if (x < nyel) {
+                        if (es + 1 < p.NE)
+                            Ys[x] = yv[u];
+                        yv[u] = zero;
+                        bool ok;
+                        const double2 *src = yaddr(x, es + 2, ok);
+                        if (ok && es + 2 < p.NE)
+                            yv[u] = *src;
+                    }
                 }
             }
             __syncthreads();
             if (es >= p.NE)
                 break;
-            // ---- phase A: the taps of step es, then the first sandwich round of es + 1
-            if (g < ngroups) {
-                int rs[kNT];
+            // ---- phase A: the MFMAs of step es (this wave's share of the orbital
+            // pairs), then the first sandwich round of es + 1
+            int roff[MT];
 #pragma unroll
-                for (int u = 0; u < kNT; ++u)
-                    rs[u] = ring_slot(es + su[u], R) * NN;
-#pragma unroll 1
-                for (int c = pp; c < NN; c += P) {
-                    double2 xx[kNT];
+            for (int mt = 0; mt < MT; ++mt)
+                roff[mt] = ring_slot(es + tap_s[mt], R) * NN;
+            for (int s = wave; s < nks; s += pik::kWaves) {
+                const int c = 2 * s + chalf;
+                const bool cok = c < NN;
+                double av[MT], bv[NTN];
 #pragma unroll
-                    for (int u = 0; u < kNT; ++u)
-                        xx[u] = ring[rs[u] + c];
-#pragma unroll
-                    for (int ij = 0; ij < kNF; ++ij) {
-                        const double2 z = Zs[ij * NN + c];
-#pragma unroll
-                        for (int u = 0; u < kNT; ++u)
-                            cmac(accr[ij][u], acci[ij][u], z.x, z.y, xx[u].x, xx[u].y);
+                for (int mt = 0; mt < MT; ++mt) {
+                    av[mt] = 0.0;
+                    if (cok && tap_ok[mt]) {
+                        const double2 v = ring[roff[mt] + c];
+                        av[mt] = xpart ? v.y : v.x;
                     }
                 }
+#pragma unroll
+                for (int nt = 0; nt < NTN; ++nt) {
+                    bv[nt] = 0.0;
+                    if (cok && bcol[nt] >= 0) {
+                        const double2 v = Zb[(size_t)c * ncol + bcol[nt]];
+                        bv[nt] = bsign[nt] * (bcomp[nt] ? v.y : v.x);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NTN; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt],
+                                                                           acc[mt][nt], 0, 0, 0);
             }
             if (es + 1 < p.NE)
-                sandwich_first(dHs, Ys, Us, NN, No, tid);
+                sandwich_first(dHs, Ys, Us, nbw, NN, No, tid);
             __syncthreads();
         }
     }
 
-    // ---- reduce each group's P partial sums in a fixed order, write beta * P
+    // ---- the waves' partial sums in a fixed order: wave w + 4 is added into
+    // wave w, then the four sums are added in wave order; then beta * P.  An
+    // MFMA accumulator holds, for lane l, rows l / 16 + 4 r of its tile at
+    // column l % 16.
+    constexpr int kHalf = pik::kWaves / 2;
+    double *red = reinterpret_cast<double *>(lds);  // [kHalf waves][16 MT][16 NTN]
+    const int rows = 16 * MT, cols = 16 * NTN;
+    auto at = [&](int v, int mt, int nt, int r) -> double & {
+        return red[((size_t)v * rows + 16 * mt + (lane >> 4) + 4 * r) * cols + 16 * nt +
+                   (lane & 15)];
+    };
     __syncthreads();
-    const int lane = tid & 63;
-    const int pw = P < 64 ? P : 64;  // partitions of one group inside a wave
+    if (wave >= kHalf) {
 #pragma unroll
-    for (int ij = 0; ij < kNF; ++ij)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int u = 0; u < kNT; ++u)
-            for (int off = pw >> 1; off > 0; off >>= 1) {
-                accr[ij][u] += __shfl_xor(accr[ij][u], off);
-                acci[ij][u] += __shfl_xor(acci[ij][u], off);
-            }
-    // waves of one group (P > 64) combine through LDS, lowest wave first
-    double2 *red = lds;  // [4 waves][kNF][kNT]
-    const int wave = tid >> 6;
-    const int wpg = P > 64 ? P / 64 : 1;  // waves per group
-    if (wpg > 1 && lane == 0) {
+            for (int nt = 0; nt < NTN; ++nt)
 #pragma unroll
-        for (int ij = 0; ij < kNF; ++ij)
-#pragma unroll
-            for (int u = 0; u < kNT; ++u)
-                red[(wave * kNF + ij) * kNT + u] = make_double2(accr[ij][u], acci[ij][u]);
+                for (int r = 0; r < 4; ++r)
+                    at(wave - kHalf, mt, nt, r) = acc[mt][nt][r];
     }
     __syncthreads();
-    if (g < ngroups && pp == 0) {
-        if (wpg > 1) {
+    if (wave < kHalf) {
 #pragma unroll
-            for (int ij = 0; ij < kNF; ++ij)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int u = 0; u < kNT; ++u) {
-                    double sr = 0.0, si = 0.0;
-                    for (int v = 0; v < wpg; ++v) {
-                        const double2 x = red[((wave + v) * kNF + ij) * kNT + u];
-                        sr += x.x;
-                        si += x.y;
-                    }
-                    accr[ij][u] = sr;
-                    acci[ij][u] = si;
-                }
+            for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[mt][nt][r] += at(wave, mt, nt, r);
+    }
+    __syncthreads();
+    if (wave < kHalf) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    at(wave, mt, nt, r) = acc[mt][nt][r];
+    }
+    __syncthreads();
+    const size_t qw_stride = (size_t)p.NA * (p.NB + 1) * kNF;
+    for (int x = tid; x < (t1 - t0) * nbv * kNF; x += kBlock) {
+        const int tt = x / (nbv * kNF), bij = x - tt * (nbv * kNF);
+        double sr = 0.0, si = 0.0;
+        for (int v = 0; v < kHalf; ++v) {
+            sr += red[((size_t)v * rows + tt) * cols + 2 * bij];
+            si += red[((size_t)v * rows + tt) * cols + 2 * bij + 1];
         }
-#pragma unroll
-        for (int u = 0; u < kNT; ++u) {
-            if (!valid[u])
-                continue;
-            const int t = t0 + g * kNT + u;
-            double2 *o = p.Pi + ((size_t)q * p.Nw + p.tw[t]) * qw_stride + out_a * kNF;
-#pragma unroll
-            for (int ij = 0; ij < kNF; ++ij)
-                o[ij] = make_double2(p.beta_re * accr[ij][u] - p.beta_im * acci[ij][u],
-                                     p.beta_re * acci[ij][u] + p.beta_im * accr[ij][u]);
-        }
+        const int b = b0 + bij / kNF, ij = bij % kNF;
+        p.Pi[((size_t)q * p.Nw + p.tw[t0 + tt]) * qw_stride + ((size_t)a * (p.NB + 1) + b) * kNF +
+             ij] = make_double2(p.beta_re * sr - p.beta_im * si, p.beta_re * si + p.beta_im * sr);
     }
 }
 
@@ -305,6 +373,24 @@ __global__ void k_pi_diag(double2 *Pi, int64_t nqwa, int NB)
     blk[NB * kNF + ij] = make_double2(-sr, -si);
 }
 
+template <int MT, int NTN>
+hipError_t launch_as(const PiParams &p, size_t lds_bytes, hipStream_t s)
+{
+    static bool done = false;
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_pi_mfma<MT, NTN>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)pik::kLdsBudgetOne);
+        if (e != hipSuccess)
+            return e;
+        done = true;
+    }
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_pi_mfma<MT, NTN>), dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s,
+                       p);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t pi_launch(const PiParams &p, size_t lds_bytes, hipStream_t s)
@@ -313,18 +399,19 @@ hipError_t pi_launch(const PiParams &p, size_t lds_bytes, hipStream_t s)
         return hipSuccess;
     if (p.n_wg > 0x7fffffffLL)
         return hipErrorInvalidConfiguration;
-    static bool done = false;
-    if (!done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_pi_fp64,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)pik::kLdsBudgetOne);
-        if (e != hipSuccess)
-            return e;
-        done = true;
+    const int ntn = (p.nbw * kNF * 2 + 15) / 16;
+    hipError_t e;
+    if (p.mtiles == 1) {
+        e = ntn <= 2 ? launch_as<1, 2>(p, lds_bytes, s)
+          : ntn == 3 ? launch_as<1, 3>(p, lds_bytes, s)
+          : ntn == 4 ? launch_as<1, 4>(p, lds_bytes, s)
+                     : launch_as<1, 5>(p, lds_bytes, s);
+    } else {
+        e = ntn <= 2 ? launch_as<2, 2>(p, lds_bytes, s)
+          : ntn == 3 ? launch_as<2, 3>(p, lds_bytes, s)
+          : ntn == 4 ? launch_as<2, 4>(p, lds_bytes, s)
+                     : launch_as<2, 5>(p, lds_bytes, s);
     }
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_pi_fp64, dim3((unsigned)p.n_wg), dim3(kBlock), lds_bytes, s, p);
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     const int64_t nqwa = (int64_t)p.Nqz * p.Nw * p.NA;

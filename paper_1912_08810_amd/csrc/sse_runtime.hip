@@ -880,11 +880,12 @@ sse_status sse_pi_submit(sse_plan_t plan, const int32_t *neigh, const double *dH
                     d.Norb);
     if (!workspace || workspace_bytes < kStatusBytes)
         return fail(SSE_ERR_ARG, "sse_pi_submit: workspace of %zu bytes needed", kStatusBytes);
-    const PiGeom gm = pi_geometry(d.Norb, I.shift, d.Nw);
+    const PiGeom gm = pi_geometry(d.Norb, d.NB, I.shift, d.Nw);
     if (!gm.ok)
         return fail(SSE_ERR_UNSUPPORTED, "sse_pi_submit: Norb=%d leaves no room for the ring",
                     d.Norb);
-    const int64_t n_wg = (int64_t)d.NA * d.NB * d.Nqz * gm.nchunk;
+    const int nbgroups = (d.NB + gm.nbw - 1) / gm.nbw;
+    const int64_t n_wg = (int64_t)d.NA * d.Nqz * nbgroups * gm.nchunk;
     if (n_wg > 0x7fffffffLL)
         return fail(SSE_ERR_SHAPE, "sse_pi_submit: %lld workgroups exceed one launch",
                     (long long)n_wg);
@@ -917,8 +918,10 @@ sse_status sse_pi_submit(sse_plan_t plan, const int32_t *neigh, const double *dH
         pp.Nw = d.Nw;
         pp.nchunk = gm.nchunk;
         pp.R = gm.R;
+        pp.nbw = gm.nbw;
+        pp.nbgroups = nbgroups;
+        pp.mtiles = gm.mtiles;
         memcpy(pp.cb, gm.cb, sizeof pp.cb);
-        memcpy(pp.cg, gm.cg, sizeof pp.cg);
         memcpy(pp.tw, gm.tw, sizeof pp.tw);
         memcpy(pp.ts, gm.ts, sizeof pp.ts);
         pp.n_wg = n_wg;

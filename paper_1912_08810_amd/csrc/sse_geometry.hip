@@ -117,14 +117,15 @@ size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int No
 }
 
 // Geometry of the phonon kernel (sse_pi.hip): the most neighbours per
-// workgroup (up to 4) whose sandwich buffers leave room for a ring of the
-// taps' rows, then the taps, sorted by increasing shift, cut into chunks of at
-// most 32 whose ring fits.  LDS per workgroup: ring R rows, per neighbour 13
-// complex128 blocks (Zt 9, U 3, Y 1) and 3 binary64 dH blocks.
+// workgroup (up to 4) whose buffers leave room for a ring of the taps' rows,
+// then the taps, sorted by increasing shift, cut into chunks of at most 32
+// whose ring fits.  LDS per workgroup: ring R + 1 rows of NNp (the pairs padded
+// to an even count) complex128 values; Zb NNp rows of 16 ntn binary64 columns;
+// per neighbour U (3 blocks) and Y (1 block) complex128 and dH (3 blocks) binary64.
 PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
 {
     PiGeom gm{};
-    const size_t NN = (size_t)Norb * Norb;
+    const size_t NN = (size_t)Norb * Norb, NNp = NN + (NN & 1);
     std::vector<int> order(Nw);
     for (int w = 0; w < Nw; ++w)
         order[w] = w;
@@ -134,12 +135,16 @@ PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
         gm.tw[t] = order[t];
         gm.ts[t] = w_shift[order[t]];
     }
-    const size_t per_nb = NN * (13 * 16 + 3 * 8), per_row = NN * 16;
+    auto ntn_of = [](int nbw) { return (nbw * 9 * 2 + 15) / 16; };
+    auto fixed_of = [&](int nbw) {
+        return NNp * 16 + NNp * 16 * ntn_of(nbw) * 8 + (size_t)nbw * NN * (3 * 16 + 16 + 3 * 8);
+    };
+    const size_t per_row = NNp * 16;
     const size_t budget = pik::kLdsBudgetOne;
     const int want_rows = std::min(gm.ts[Nw - 1] - gm.ts[0] + 1, 8);
     int rmax = 0;
     for (gm.nbw = std::min(NB, pik::kMaxNbw); gm.nbw >= 1; --gm.nbw) {
-        const size_t fixed = per_nb * gm.nbw;
+        const size_t fixed = fixed_of(gm.nbw);
         rmax = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
         if (rmax >= want_rows || gm.nbw == 1)
             break;
@@ -160,10 +165,9 @@ PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
     }
     gm.cb[gm.nchunk] = Nw;
     gm.mtiles = maxtaps <= 16 ? 1 : 2;
-    const int ntn = (gm.nbw * 9 * 2 + 15) / 16;
     // the final reduction reuses LDS for half the waves' accumulator tiles
-    gm.lds_bytes = std::max((size_t)gm.R * per_row + per_nb * gm.nbw,
-                            (size_t)(pik::kWaves / 2) * 16 * gm.mtiles * 16 * ntn * 8);
+    gm.lds_bytes = std::max((size_t)gm.R * per_row + fixed_of(gm.nbw),
+                            (size_t)(pik::kWaves / 2) * 16 * gm.mtiles * 16 * ntn_of(gm.nbw) * 8);
     gm.ok = rmax >= 1 && gm.lds_bytes <= budget;
     return gm;
 }

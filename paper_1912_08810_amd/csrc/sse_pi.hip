@@ -61,18 +61,26 @@ __device__ __forceinline__ int ring_slot(int row, int R)
     return m < 0 ? m + R : m;
 }
 
-// First sandwich round: U[b][j][p][m] = sum_r dH_bj[p][r] Y_b[r][m]; a thread
-// takes one (b, p, m) and all three j, sharing the loads of Y's column.
-__device__ __forceinline__ void sandwich_first(const double *dHs, const double2 *Ys, double2 *Us,
-                                               int nbw, int NN, int No, int tid)
+// Per-thread offsets of the two sandwich rounds and of the Y staging; a
+// thread's tasks are the same at every step (at most two each, since
+// nbw Norb^2 <= 1024 = 2 kBlock), so their index arithmetic is done once.
+struct SandwichTasks {
+    int n1, n2, ny;                 // tasks of round 1, round 2, staged Y elements
+    int h1[2], y1[2], o1[2];        // round 1: dH row, Y column, U output
+    int h2[2], u2[2], o2[2];        // round 2: dH rows, U rows, Zb output (double index)
+    int ys[2], yg[2];               // Y staging: LDS slot, element offset in a G energy row (-1: zero)
+};
+
+// First sandwich round: U[b][j][p][m] = sum_r dH_bj[p][r] Y_b[r][m]; a task is
+// one (b, p, m) for all three j, sharing the loads of Y's column.
+__device__ __forceinline__ void sandwich_first(const SandwichTasks &T, const double *dHs,
+                                               const double2 *Ys, double2 *Us, int NN, int No)
 {
-#pragma unroll 1
-    for (int o = tid; o < nbw * NN; o += kBlock) {
-        const int b = o / NN, rem = o - b * NN, r0 = rem / No, m = rem - r0 * No;
-        const double *h = dHs + (size_t)b * 3 * NN + r0 * No;
-        const double2 *y = Ys + (size_t)b * NN + m;
+    for (int u = 0; u < T.n1; ++u) {
+        const double *h = dHs + T.h1[u];
+        const double2 *y = Ys + T.y1[u];
         double ur[3] = {0.0, 0.0, 0.0}, ui[3] = {0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll 1
         for (int r = 0; r < No; ++r) {
             const double2 v = y[r * No];
 #pragma unroll
@@ -84,36 +92,32 @@ __device__ __forceinline__ void sandwich_first(const double *dHs, const double2 
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            Us[((size_t)b * 3 + j) * NN + rem] = make_double2(ur[j], ui[j]);
+            Us[T.o1[u] + j * NN] = make_double2(ur[j], ui[j]);
     }
 }
 
-// Second round: Zb[c][b 9 + 3 i + j] = Zt_bij[n][p] = sum_m dH_bi[n][m] U[b][j][p][m],
-// c = n Norb + p (the orbital pair of X it multiplies); a thread takes one
-// (c, b) and all nine (i, j), sharing the loads of the three dH rows and the
-// three U rows.
-__device__ __forceinline__ void sandwich_second(const double *dHs, const double2 *Us, double2 *Zb,
-                                                int nbw, int NN, int No, int tid)
+// Second round: Zt_bij[n][p] = sum_m dH_bi[n][m] U[b][j][p][m] into the column
+// pair 2 (9 b + 3 i + j) + (re, im) of row c = n Norb + p of Zb (the orbital pair
+// of X it multiplies); a task is one (c, b) for all nine (i, j), sharing the
+// loads of the three dH rows and the three U rows.
+__device__ __forceinline__ void sandwich_second(const SandwichTasks &T, const double *dHs,
+                                                const double2 *Us, double *Zb, int NN, int No)
 {
-    const int ncol = nbw * kNF;
-#pragma unroll 1
-    for (int o = tid; o < NN * nbw; o += kBlock) {
-        const int c = o / nbw, b = o - c * nbw;
-        const int n = c / No, r0 = c - n * No;
-        const double *h = dHs + (size_t)b * 3 * NN + n * No;
-        const double2 *u = Us + (size_t)b * 3 * NN + r0 * No;
+    for (int u = 0; u < T.n2; ++u) {
+        const double *h = dHs + T.h2[u];
+        const double2 *us = Us + T.u2[u];
         double zr[kNF], zi[kNF];
 #pragma unroll
         for (int x = 0; x < kNF; ++x)
             zr[x] = zi[x] = 0.0;
-#pragma unroll 2
+#pragma unroll 1
         for (int m = 0; m < No; ++m) {
             double hi[3];
             double2 uj[3];
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
                 hi[t] = h[t * NN + m];
-                uj[t] = u[t * NN + m];
+                uj[t] = us[t * NN + m];
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -123,7 +127,7 @@ __device__ __forceinline__ void sandwich_second(const double *dHs, const double2
                     zi[3 * i + j] = fma(hi[i], uj[j].y, zi[3 * i + j]);
                 }
         }
-        double2 *out = Zb + (size_t)c * ncol + b * kNF;
+        double2 *out = reinterpret_cast<double2 *>(Zb + T.o2[u]);
 #pragma unroll
         for (int x = 0; x < kNF; ++x)
             out[x] = make_double2(zr[x], zi[x]);
@@ -134,10 +138,12 @@ template <int MT, int NTN>
 __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
 {
     extern __shared__ double2 lds[];
-    const int NN = p.NN, No = p.Norb, R = p.R, nbw = p.nbw, ncol = nbw * kNF;
-    double2 *ring = lds;                          // [R][NN]
-    double2 *Zb = ring + (size_t)R * NN;          // [NN][nbw 9]
-    double2 *Us = Zb + (size_t)NN * ncol;         // [nbw 3][NN]
+    constexpr int ZC = 16 * NTN;                  // Zb row: 2 (b, i, j) columns, padded
+    const int NN = p.NN, No = p.Norb, R = p.R, nbw = p.nbw;
+    const int NNp = NN + (NN & 1);                // orbital pairs padded to an even count
+    double2 *ring = lds;                          // [R + 1][NNp]; row R and pair NN are zero
+    double *Zb = reinterpret_cast<double *>(ring + (size_t)(R + 1) * NNp);  // [NNp][ZC]
+    double2 *Us = reinterpret_cast<double2 *>(Zb + (size_t)NNp * ZC);     // [nbw 3][NN]
     double2 *Ys = Us + (size_t)nbw * 3 * NN;      // [nbw][NN]
     double *dHs = reinterpret_cast<double *>(Ys + (size_t)nbw * NN);  // [nbw 3][NN]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -158,6 +164,36 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         const int b = x / (3 * NN);
         dHs[x] = b < nbv ? p.dH[((size_t)a * p.NB + b0) * 3 * NN + x] : 0.0;
     }
+    // zero once: the ring's zero row and padding pair, Zb's padding row and columns
+    for (int x = tid; x < (R + 1) * NNp; x += kBlock)
+        ring[x] = make_double2(0.0, 0.0);
+    for (int x = tid; x < NNp * ZC; x += kBlock)
+        Zb[x] = 0.0;
+
+    SandwichTasks T;
+    T.n1 = T.n2 = T.ny = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int o = tid + u * kBlock;
+        if (o < nbw * NN) {
+            // round 1 and Y staging: o = (b, p, m)
+            const int b = o / NN, rem = o - b * NN, r0 = rem / No, m = rem - r0 * No;
+            T.h1[u] = b * 3 * NN + r0 * No;
+            T.y1[u] = b * NN + m;
+            T.o1[u] = b * 3 * NN + rem;
+            T.n1 = u + 1;
+            const int f = b < nbv ? p.neigh[(size_t)a * p.NB + b0 + b] : -1;
+            T.ys[u] = o;
+            T.yg[u] = (f >= 0 && f < p.NA) ? f * NN + rem : -1;
+            T.ny = u + 1;
+            // round 2: o = (c, b)
+            const int c = o / nbw, b2 = o - c * nbw, n = c / No, r2 = c - n * No;
+            T.h2[u] = b2 * 3 * NN + n * No;
+            T.u2[u] = b2 * 3 * NN + r2 * No;
+            T.o2[u] = c * ZC + 2 * kNF * b2;
+            T.n2 = u + 1;
+        }
+    }
 
     // per lane: its tap row in each row tile, its K' slot, its columns
     const int kq = lane >> 4, xpart = kq & 1, chalf = kq >> 1;
@@ -169,17 +205,16 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         tap_ok[mt] = t < t1;
         tap_s[mt] = tap_ok[mt] ? p.ts[t] : s_lo;
     }
-    int bcol[NTN];     // column (b, i, j) of this lane in each column tile, -1 = padding
-    int bcomp[NTN];    // component of Zt it reads: re (0) or im (1)
-    double bsign[NTN];
+    // B operand: x re reads (Z re, Z im) for the columns (re, im); x im reads
+    // (-Z im, Z re), the neighbouring column of the pair with a sign (applied
+    // by flipping the sign bit)
+    int bsrc[NTN];
+    unsigned bsign[NTN];
 #pragma unroll
     for (int nt = 0; nt < NTN; ++nt) {
-        const int col = 16 * nt + (lane & 15), bij = col >> 1, op = col & 1;
-        const bool ok = bij < nbv * kNF;
-        bcol[nt] = ok ? bij : -1;
-        // x re: (out re <- Z re, out im <- Z im); x im: (out re <- -Z im, out im <- Z re)
-        bcomp[nt] = xpart ^ op;
-        bsign[nt] = (xpart && !op) ? -1.0 : 1.0;
+        const int col = 16 * nt + (lane & 15);
+        bsrc[nt] = xpart ? (col ^ 1) : col;
+        bsign[nt] = (xpart && !(col & 1)) ? 0x80000000u : 0u;
     }
     v4d acc[MT][NTN];
 #pragma unroll
@@ -190,53 +225,43 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
 
     const size_t row_stride = (size_t)p.NA * NN;  // one energy step of G
     const double2 zero = make_double2(0.0, 0.0);
-    const int nks = (NN + 1) >> 1;                // MFMA steps (two orbital pairs each) per energy
-    const int nyel = nbw * NN;                    // staged Y elements per step
+    const int nks = NNp >> 1;                     // MFMA steps (two orbital pairs each) per energy
+    const double *ringd = reinterpret_cast<const double *>(ring);
 
     for (int k = 0; k < p.Nkz; ++k) {
         const int kx = (k + q) % p.Nkz;
         const double2 *Xk = p.X + ((size_t)kx * p.NE * p.NA + a) * NN;
         const double2 *Yk = p.Y + (size_t)k * p.NE * row_stride;
-        // Y element x of energy e (neighbour x / NN of the group, pair x % NN);
-        // ok = false for a padding slot or an invalid neighbour (then zero)
-        auto yaddr = [&](int x, int e, bool &ok) -> const double2 * {
-            const int b = x / NN, c = x - b * NN;
-            const int f = b < nbv ? p.neigh[(size_t)a * p.NB + b0 + b] : -1;
-            ok = f >= 0 && f < p.NA;
-            return Yk + (size_t)e * row_stride + (size_t)(ok ? f : 0) * NN + c;
-        };
         __syncthreads();  // the previous k's last step is done with the ring, Us and Ys
         // ring rows s_lo .. s_hi - 1 (step 0's rows but its top one); Y of step 0
         for (int x = tid; x < (s_hi - s_lo) * NN; x += kBlock) {
             const int row = s_lo + x / NN, c = x % NN;
-            ring[ring_slot(row, R) * NN + c] =
+            ring[ring_slot(row, R) * NNp + c] =
                 (row >= 0 && row < p.NE) ? Xk[(size_t)row * row_stride + c] : zero;
         }
         double2 yv[kYP], xv = zero;  // rows in flight: Y of a later step, the ring's next top row
 #pragma unroll
         for (int u = 0; u < kYP; ++u) {
-            const int x = tid + u * kBlock;
             yv[u] = zero;
-            if (x < nyel) {
-                bool ok;
-                const double2 *src = yaddr(x, 0, ok);
-                Ys[x] = ok ? *src : zero;
+            if (u < T.ny) {
+                const bool ok = T.yg[u] >= 0;
+                Ys[T.ys[u]] = ok ? Yk[T.yg[u]] : zero;
                 if (ok && 1 < p.NE)
-                    yv[u] = src[row_stride];
+                    yv[u] = Yk[row_stride + T.yg[u]];
             }
         }
         if (tid < NN && s_hi >= 0 && s_hi < p.NE)
             xv = Xk[(size_t)s_hi * row_stride + tid];
         __syncthreads();
-        sandwich_first(dHs, Ys, Us, nbw, NN, No, tid);
+        sandwich_first(T, dHs, Ys, Us, NN, No);
         __syncthreads();
         for (int es = 0;; ++es) {
             // ---- phase B: second sandwich round of step es; the ring's top row
             // for step es and Y of step es + 1 go to LDS; the next rows load
             if (es < p.NE) {
-                sandwich_second(dHs, Us, Zb, nbw, NN, No, tid);
+                sandwich_second(T, dHs, Us, Zb, NN, No);
                 if (tid < NN) {
-                    ring[ring_slot(es + s_hi, R) * NN + tid] = xv;
+                    ring[ring_slot(es + s_hi, R) * NNp + tid] = xv;
                     xv = zero;
                     const int row = es + 1 + s_hi;
                     if (row >= 0 && row < p.NE)
@@ -244,15 +269,12 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
                 }
 #pragma unroll
                 for (int u = 0; u < kYP; ++u) {
-                    const int x = tid + u * kBlock;
-                    if (x < nyel) {
+                    if (u < T.ny) {
                         if (es + 1 < p.NE)
-                            Ys[x] = yv[u];
+                            Ys[T.ys[u]] = yv[u];
                         yv[u] = zero;
-                        bool ok;
-                        const double2 *src = yaddr(x, es + 2, ok);
-                        if (ok && es + 2 < p.NE)
-                            yv[u] = *src;
+                        if (T.yg[u] >= 0 && es + 2 < p.NE)
+                            yv[u] = Yk[(size_t)(es + 2) * row_stride + T.yg[u]];
                     }
                 }
             }
@@ -260,40 +282,38 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
             if (es >= p.NE)
                 break;
             // ---- phase A: the MFMAs of step es (this wave's share of the orbital
-            // pairs), then the first sandwich round of es + 1
-            int roff[MT];
+            // pairs; the other wave on the SIMD covers the operand loads), then the
+            // first sandwich round of es + 1
+            int ia[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                roff[mt] = ring_slot(es + tap_s[mt], R) * NN;
+                ia[mt] = ((tap_ok[mt] ? ring_slot(es + tap_s[mt], R) : R) * NNp +
+                          2 * wave + chalf) * 2 + xpart;
+            int ib = (2 * wave + chalf) * ZC;
+            constexpr int da = 4 * pik::kWaves;   // doubles between a lane's A operands
+            const int db = 2 * pik::kWaves * ZC;
             for (int s = wave; s < nks; s += pik::kWaves) {
-                const int c = 2 * s + chalf;
-                const bool cok = c < NN;
                 double av[MT], bv[NTN];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    av[mt] = 0.0;
-                    if (cok && tap_ok[mt]) {
-                        const double2 v = ring[roff[mt] + c];
-                        av[mt] = xpart ? v.y : v.x;
-                    }
-                }
+                for (int mt = 0; mt < MT; ++mt)
+                    av[mt] = ringd[ia[mt]];
 #pragma unroll
-                for (int nt = 0; nt < NTN; ++nt) {
-                    bv[nt] = 0.0;
-                    if (cok && bcol[nt] >= 0) {
-                        const double2 v = Zb[(size_t)c * ncol + bcol[nt]];
-                        bv[nt] = bsign[nt] * (bcomp[nt] ? v.y : v.x);
-                    }
-                }
+                for (int nt = 0; nt < NTN; ++nt)
+                    bv[nt] = __hiloint2double(__double2hiint(Zb[ib + bsrc[nt]]) ^ (int)bsign[nt],
+                                              __double2loint(Zb[ib + bsrc[nt]]));
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int nt = 0; nt < NTN; ++nt)
                         acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt],
                                                                            acc[mt][nt], 0, 0, 0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    ia[mt] += da;
+                ib += db;
             }
             if (es + 1 < p.NE)
-                sandwich_first(dHs, Ys, Us, nbw, NN, No, tid);
+                sandwich_first(T, dHs, Ys, Us, NN, No);
             __syncthreads();
         }
     }

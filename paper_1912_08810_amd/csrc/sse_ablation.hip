@@ -92,17 +92,24 @@ __global__ void k_abl_dhd(AblParams p, int a0, int nat)
     p.N[x] = make_double2(sr, si);
 }
 
-// One workgroup per (atom of the chunk, k, energy tile): 4 waves, wave t owns
-// rows 16 t .. 16 t + 15 of the TE Norb (<= 64) rows (e, m) and every column
-// tile of the 2 Norb columns (n, re/im).
-__global__ __launch_bounds__(256, 1) void k_abl_gemm(AblParams p, int a0)
+// One workgroup per (atom of the chunk, k, energy tile): 8 waves, wave t owns
+// rows 16 t .. 16 t + 15 of the TE Norb (<= 128) rows (e, m) and both column
+// tiles of the 2 Norb columns (n, re/im); two waves per SIMD.  Per (b, i, q)
+// the window of M_i rows and the stacked N_i[q, :] are staged into LDS in
+// ready-made form: the window with a zero row (the padding rows' operand), N_i
+// as binary64 rows of 32 columns (n, re/im) with zero padding, so an operand is
+// one 8-byte LDS read and, for the imaginary part of M, a sign flip.
+__global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int a0)
 {
     extern __shared__ double2 lds[];
+    constexpr int ZC = 16 * pik::kAblNT;           // N row: 2 Norb columns, padded
     const int NN = p.NN, No = p.Norb, TE = p.TE;
     const int nrow = p.win_rows;                   // TE + shift spread
-    double2 *win = lds;                            // [nrow][NN]: M_i rows of the window
-    double2 *nb = win + (size_t)nrow * NN;         // [Nw Norb][Norb]: N_i[q, w][l][n]
-    int *rowoff = reinterpret_cast<int *>(nb + (size_t)p.Nw * NN);  // [Nw]: (smax - s_w) NN
+    double2 *win = lds;                            // [nrow + 1][NN]: M_i rows, then a zero row
+    double *nb = reinterpret_cast<double *>(win + (size_t)(nrow + 1) * NN);  // [Kp][ZC]
+    const int Kcount = p.Nw * No;                  // complex K entries (w, l)
+    const int Kp = Kcount + (Kcount & 1);
+    int *rowoff = reinterpret_cast<int *>(nb + (size_t)Kp * ZC);  // [Nw]: (smax - s_w) NN
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     int64_t L = blockIdx.x;
@@ -113,21 +120,36 @@ __global__ __launch_bounds__(256, 1) void k_abl_gemm(AblParams p, int a0)
     const int a = a0 + al;
     const int e0 = et * TE;
     const int te = min(TE, p.NE - e0);
-    for (int w = tid; w < p.Nw; w += 256)
+    for (int w = tid; w < p.Nw; w += pik::kAblBlock)
         rowoff[w] = (p.smax - p.shift[w]) * NN;
+    for (int x = tid; x < NN; x += pik::kAblBlock)
+        win[(size_t)nrow * NN + x] = make_double2(0.0, 0.0);
+    for (int x = tid; x < Kp * ZC; x += pik::kAblBlock)
+        nb[x] = 0.0;
 
-    // this lane's A row (e, m) and B column (n, part) within its tiles
+    // this lane's A row (e, m), K' slot and B column
     const int arow = 16 * wave + (lane & 15);
     const bool arow_ok = arow < TE * No;
     const int ae = arow_ok ? arow / No : 0, am = arow_ok ? arow - ae * No : 0;
-    const int kq = lane >> 4;            // K' index within an MFMA step: (Kc half, re/im)
-    const int xpart = kq & 1;            // part of M (the A operand) this lane carries
-    const int Kcount = p.Nw * No;        // complex K entries (w, l)
+    const int kq = lane >> 4, xpart = kq & 1, chalf = kq >> 1;
+    // A: M window element (row of e - s_w, m, l), part xpart; padding rows read the zero row
+    const int abase = arow_ok ? (ae * NN + am * No) * 2 + xpart : nrow * NN * 2;
+    const int arow_step = arow_ok ? 1 : 0;       // padding lanes stay on the zero row
+    // B: x re reads (N re, N im) for the columns (re, im); x im reads (-N im, N re)
+    int bsrc[pik::kAblNT];
+    unsigned bsign[pik::kAblNT];
+#pragma unroll
+    for (int t = 0; t < pik::kAblNT; ++t) {
+        const int col = 16 * t + (lane & 15);
+        bsrc[t] = xpart ? (col ^ 1) : col;
+        bsign[t] = (xpart && !(col & 1)) ? 0x80000000u : 0u;
+    }
     v4d acc[pik::kAblNT];
 #pragma unroll
     for (int t = 0; t < pik::kAblNT; ++t)
         acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
-    const int ncol = 2 * No;
+    const double *wind = reinterpret_cast<const double *>(win);
+    const int nks = Kp >> 1;
 
     for (int b = 0; b < p.NB; ++b) {
         for (int i = 0; i < kN3D; ++i) {
@@ -139,42 +161,39 @@ __global__ __launch_bounds__(256, 1) void k_abl_gemm(AblParams p, int a0)
                 const double2 *Mrow = p.M + ((((size_t)al * p.NB + b) * kN3D + i) * p.Nkz + kk) *
                                                 (size_t)p.NE * NN;
                 const int ebase = e0 - p.smax;
-                for (int x = tid; x < nrow * NN; x += 256) {
+                for (int x = tid; x < nrow * NN; x += pik::kAblBlock) {
                     const int r = x / NN, c = x - r * NN;
                     const int e = ebase + r;
                     win[x] = (e >= 0 && e < p.NE) ? Mrow[(size_t)e * NN + c] : make_double2(0.0, 0.0);
                 }
                 const double2 *Nq = p.N + ((((size_t)al * p.NB + b) * kN3D + i) * p.Nqz + q) *
                                               (size_t)p.Nw * NN;
-                for (int x = tid; x < p.Nw * NN; x += 256)
-                    nb[x] = Nq[x];
+                for (int x = tid; x < Kcount * No; x += pik::kAblBlock) {
+                    const int kc = x / No, n = x - kc * No;
+                    const double2 v = Nq[x];
+                    nb[kc * ZC + 2 * n] = v.x;
+                    nb[kc * ZC + 2 * n + 1] = v.y;
+                }
                 __syncthreads();
-                // K loop: step s covers complex K entries 2 s and 2 s + 1
-                int Kc = kq >> 1;            // this lane's complex K entry
-                int w = 0, l = Kc;
+                // K loop: step s covers complex K entries 2 s and 2 s + 1 = (w, l)
+                int Kc = chalf, w = 0, l = Kc;
                 while (l >= No) {
                     l -= No;
                     ++w;
                 }
-                for (; Kc - (kq >> 1) < Kcount; Kc += 2) {
-                    const bool kok = Kc < Kcount;
-                    double av = 0.0;
-                    if (kok && arow_ok) {
-                        const double2 m = win[rowoff[w] + ae * NN + am * No + l];
-                        av = xpart ? m.y : m.x;
-                    }
+                int ib = Kc * ZC;
+                for (int s = 0; s < nks; ++s) {
+                    // the padding K entry (Kcount odd) reads a zero N row
+                    const int wc = w < p.Nw ? w : 0;
+                    const double av = wind[abase + arow_step * ((rowoff[wc] + l) * 2)];
 #pragma unroll
                     for (int t = 0; t < pik::kAblNT; ++t) {
-                        const int col = 16 * t + (lane & 15);
-                        double bv = 0.0;
-                        if (kok && col < ncol) {
-                            const int n = col >> 1, opart = col & 1;
-                            const double2 v = nb[(size_t)Kc * No + n];
-                            // x re: (re <- N re, im <- N im); x im: (re <- -N im, im <- N re)
-                            bv = xpart ? (opart ? v.x : -v.y) : (opart ? v.y : v.x);
-                        }
+                        const double x = nb[ib + bsrc[t]];
+                        const double bv = __hiloint2double(__double2hiint(x) ^ (int)bsign[t],
+                                                           __double2loint(x));
                         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
                     }
+                    ib += 2 * ZC;
                     l += 2;
                     while (l >= No) {
                         l -= No;
@@ -188,17 +207,16 @@ __global__ __launch_bounds__(256, 1) void k_abl_gemm(AblParams p, int a0)
     // its tile, column lane % 16), then alpha (re + i im) -> Sigma, coalesced
     __syncthreads();
     double *cs = reinterpret_cast<double *>(lds);
-    const int cstride = 16 * pik::kAblNT;
 #pragma unroll
     for (int t = 0; t < pik::kAblNT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            cs[(16 * wave + (lane >> 4) + 4 * r) * cstride + 16 * t + (lane & 15)] = acc[t][r];
+            cs[(16 * wave + (lane >> 4) + 4 * r) * ZC + 16 * t + (lane & 15)] = acc[t][r];
     __syncthreads();
     double2 *S = p.Sigma + (((size_t)k * p.NE + e0) * p.NA + a) * NN;
-    for (int x = tid; x < te * NN; x += 256) {
+    for (int x = tid; x < te * NN; x += pik::kAblBlock) {
         const int e = x / NN, c = x - e * NN, m = c / No, n = c - m * No;
-        const double cr = cs[(e * No + m) * cstride + 2 * n], ci = cs[(e * No + m) * cstride + 2 * n + 1];
+        const double cr = cs[(e * No + m) * ZC + 2 * n], ci = cs[(e * No + m) * ZC + 2 * n + 1];
         S[(size_t)e * p.NA * NN + c] = make_double2(p.alpha_re * cr - p.alpha_im * ci,
                                                     p.alpha_re * ci + p.alpha_im * cr);
     }
@@ -227,7 +245,8 @@ hipError_t ablation_launch(const AblParams &p, size_t lds_bytes, int chunk_atoms
         hipLaunchKernelGGL(k_abl_dhg, dim3(nblk(nm)), dim3(256), 0, s, p, a0, nat);
         hipLaunchKernelGGL(k_abl_dhd, dim3(nblk(nn)), dim3(256), 0, s, p, a0, nat);
         const int64_t nwg = (int64_t)nat * p.Nkz * p.n_etiles;
-        hipLaunchKernelGGL(k_abl_gemm, dim3((unsigned)nwg), dim3(256), lds_bytes, s, p, a0);
+        hipLaunchKernelGGL(k_abl_gemm, dim3((unsigned)nwg), dim3(pik::kAblBlock), lds_bytes, s, p,
+                           a0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -236,7 +236,8 @@ PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw);
 // Norb x Norb Nw x Norb GEMMs on the matrix cores.
 namespace pik {
 constexpr int kAblNT = 2;       // column tiles of 16: 2 Norb <= 32
-constexpr int kAblRows = 64;    // rows (e, m) per workgroup: 4 waves x 16
+constexpr int kAblBlock = 512;  // 8 waves, two per SIMD
+constexpr int kAblRows = 128;   // rows (e, m) per workgroup: 8 waves x 16
 }  // namespace pik
 struct AblParams {
     const int32_t *neigh;

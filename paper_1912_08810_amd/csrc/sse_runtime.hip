@@ -1036,7 +1036,9 @@ sse_status sse_ablation_compute(sse_plan_t plan, const int32_t *neigh, const dou
     p.win_rows = p.TE + smax - smin;
     p.alpha_re = d.alpha_re;
     p.alpha_im = d.alpha_im;
-    const size_t lds = std::max(((size_t)p.win_rows * NN + (size_t)d.Nw * NN) * 16 + 4 * d.Nw,
+    const size_t kp = (size_t)d.Nw * d.Norb + ((size_t)d.Nw * d.Norb & 1);
+    const size_t lds = std::max((size_t)(p.win_rows + 1) * NN * 16 + kp * 16 * pik::kAblNT * 8 +
+                                    4 * (size_t)d.Nw,
                                 (size_t)pik::kAblRows * 16 * pik::kAblNT * 8);
     if (lds > pik::kLdsBudgetOne)
         return fail(SSE_ERR_UNSUPPORTED,

@@ -43,7 +43,8 @@ def parse():
                          "(0 = skip)")
     ap.add_argument("--only", default="",
                     help="time only this part, e.g. for profiling: a precision form (fp64, "
-                         "fp32, bf16x3, fp64c64, fp64ah) or a section (pi, ablation, aux)")
+                         "fp32, bf16x3, fp64c64, fp64ah) or a section (pi, ablation, aux, "
+                         "serving, batch)")
     ap.add_argument("--pi-steps", type=int, default=2,
                     help="timed steps of the phonon self-energy (Eqs. (4)-(5)) at device "
                          "scale, both components (0 = skip)")
@@ -54,10 +55,17 @@ def parse():
     ap.add_argument("--batch", default="fp64,bf16x3",
                     help="precisions of the 48-instance batched run ('' = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=200.0)
-    ap.add_argument("--serving-jobs", type=int, default=8,
-                    help="jobs of the serving run (0 = skip)")
-    ap.add_argument("--serving-half-load", action="store_true",
-                    help="also serve at half the measured capacity (service latency)")
+    ap.add_argument("--serving-jobs", type=int, default=24,
+                    help="jobs of the saturated serving run (0 = skip the serving section)")
+    ap.add_argument("--serving-half-jobs", type=int, default=8,
+                    help="jobs of the run at half the measured capacity (service latency; "
+                         "0 = skip)")
+    ap.add_argument("--serving-small-jobs", type=int, default=48,
+                    help="jobs of each of the small-job and tiny-job mixes, served "
+                         "concurrently and one at a time (0 = skip)")
+    ap.add_argument("--serving-plain-jobs", type=int, default=4,
+                    help="jobs (the first of the saturated run's) timed on the plain per-job "
+                         "path")
     ap.add_argument("--profile-steps", action="store_true",
                     help="print a progress line per step (for profiler runs)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -305,7 +313,7 @@ def configs_seed():
 
 def batch_section(args, torch, sse, configs, DeviceProblem, log):
     """48 uneven instances (one component each) in HBM-budgeted waves; each wave
-    is one persistent launch; tile shapes from the autotuner's cache."""
+    is one persistent launch; tile shapes and tap chunks from the autotuner's cache."""
     from paper_1912_08810_amd import autotune
     cache = autotune.load_cache()
     insts = configs.batch_instances(configs.SEED, 48)
@@ -313,9 +321,11 @@ def batch_section(args, torch, sse, configs, DeviceProblem, log):
     for name in [x for x in args.batch.split(",") if x]:
         prec = {"fp64": sse.FP64, "fp32": sse.FP32, "bf16x3": sse.BF16X3}[name]
         esz = 16 if prec == sse.FP64 else 8
-        tiles = {i: autotune.tile_for(prec, p.Norb, p.NE, p.Nw, cache) for i, p in enumerate(insts)}
+        tuned = {i: autotune.params_for(prec, p.Norb, p.NE, p.Nw, cache)
+                 for i, p in enumerate(insts)}
         descs_all = {i: sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw, prec=prec,
-                                      tile_e=tiles[i]) for i, p in enumerate(insts)}
+                                      tile_e=tuned[i][0], chunk_taps=tuned[i][1])
+                     for i, p in enumerate(insts)}
         # resident bytes of one instance: G, Sigma, D~, dH and its plan workspace
         # (A fragments and the split copy of G on the MFMA paths)
         per = lambda i: ((2 * insts[i].g_elems() + insts[i].d_elems()) * esz
@@ -382,8 +392,11 @@ def batch_section(args, torch, sse, configs, DeviceProblem, log):
 def serving_section(args, torch, sse, configs, log):
     """Jobs from the batch size distribution, Poisson arrivals at 200 jobs/s,
     10 SCBA iterations each, complex64 (bf16 hi/lo MFMA) at the fp32 tolerance
-    with binary64 fallback; compared with the plain per-job path (binary64, one
-    job at a time, inputs copied in and results out every iteration)."""
+    with binary64 fallback; then the same mix at half the measured capacity
+    (service latency); compared with the plain per-job path (binary64, one job
+    at a time, inputs copied in and results out every iteration) and with the
+    same resident loop serving one job at a time.  A mix of small jobs that do
+    not fill the GPU is served both ways too."""
     from paper_1912_08810_amd import serving
     from ssegen.device_problem import DeviceProblem
     probs = configs.batch_instances(configs.SEED + 1, args.serving_jobs)
@@ -393,13 +406,24 @@ def serving_section(args, torch, sse, configs, log):
     sat = serving.summarize(res)
     out = {"saturated": dict(sat, arrival_rate=200.0, label="saturated (offered load far above "
                              "capacity; latency is queueing-dominated)")}
-    # plain per-job path over the same jobs (each iteration costs the same, so two
+    del srv
+    torch.cuda.empty_cache()
+    if args.serving_half_jobs > 0:
+        # service latency: the first jobs of the mix offered at half the capacity
+        # just measured (Poisson, seeded)
+        rate = 0.5 * sat["jobs_per_s"]
+        jobs2 = serving.make_jobs(probs[:args.serving_half_jobs], rate=rate,
+                                  seed=configs.SEED + 7)
+        r2 = serving.Server(budget_bytes=200e9, slots=4, prec=sse.BF16X3, tol=1e-5).run(
+            jobs2, log=log)
+        out["half_capacity"] = dict(serving.summarize(r2), arrival_rate=round(rate, 4),
+                                    label="half the measured capacity (service latency)")
+        torch.cuda.empty_cache()
+    # plain per-job path over the first jobs (each iteration costs the same, so two
     # iterations per job): host -> device copies of G and D~ (complex128),
     # binary64 compute, Sigma back to the host, every iteration, one job at a time
     plain_iters = 2
     t_plain, flops_plain = 0.0, 0.0
-    del srv
-    torch.cuda.empty_cache()
     # host data in ordinary memory, moved through two fixed pinned staging
     # buffers: the host copy into one overlaps the DMA out of the other
     CH = 1 << 25  # float64 elements per staging buffer (256 MiB)
@@ -431,7 +455,8 @@ def serving_section(args, torch, sse, configs, log):
         done[(len(chunks) - 1) & 1].synchronize()
         host[j:j + min(CH, dev.numel() - j)].copy_(stage[(len(chunks) - 1) & 1][:min(CH, dev.numel() - j)])
 
-    for p in probs:
+    plain_probs = probs[:args.serving_plain_jobs]
+    for p in plain_probs:
         dp = DeviceProblem(p, 77, ncomp=2)
         hG, hD, hS = dp.G.cpu(), dp.D.cpu(), torch.empty(dp.Sigma.shape, dtype=dp.Sigma.dtype)
         desc = sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw, ncomp=2,
@@ -454,26 +479,48 @@ def serving_section(args, torch, sse, configs, log):
         torch.cuda.empty_cache()
     del stage
     plain_tflops = flops_plain / t_plain / 1e12
-    log(f"plain per-job: {plain_tflops:.2f} TFLOP/s over {len(probs)} jobs")
-    # serial resident complex64 (one slot), same jobs: isolates the gain of
-    # overlapping jobs
+    log(f"plain per-job: {plain_tflops:.2f} TFLOP/s over {len(plain_probs)} jobs")
+    # the same resident complex64 loop with one slot over the same jobs: isolates
+    # the gain of overlapping jobs
     serial = serving.Server(budget_bytes=200e9, slots=1, prec=sse.BF16X3, tol=1e-5)
     j0 = serving.make_jobs(probs, rate=1e9, seed=configs.SEED, iterations=plain_iters)
     rs = serial.run(j0, log=log)
     ser = serving.summarize(rs)
     out["plain_per_job"] = {"tflops": round(plain_tflops, 3), "s": round(t_plain, 3),
-                            "jobs": len(probs), "iterations_per_job": plain_iters,
+                            "jobs": len(plain_probs), "iterations_per_job": plain_iters,
                             "path": "fp64, one job at a time; G, D~ in and Sigma out every "
                                     "iteration through two 256 MiB pinned staging buffers"}
     out["serial_resident_c64"] = {"tflops": ser["tflops"], "jobs": ser["jobs"],
                                   "iterations_per_job": plain_iters}
     out["speedup_vs_plain"] = round(sat["tflops"] / plain_tflops, 2)
     out["speedup_vs_serial_resident"] = round(sat["tflops"] / ser["tflops"], 2)
-    if args.serving_half_load:
-        rate = 0.5 * sat["jobs_per_s"]
-        jobs2 = serving.make_jobs(probs, rate=rate, seed=configs.SEED + 7)
-        r2 = serving.Server(budget_bytes=200e9, slots=4, prec=sse.BF16X3, tol=1e-5).run(jobs2)
-        out["half_capacity"] = dict(serving.summarize(r2), arrival_rate=round(rate, 4))
+    if args.serving_small_jobs > 0:
+        # small jobs (each launch still has thousands of output tiles, but lasts a
+        # millisecond or less) and tiny jobs (fewer output tiles than compute
+        # units: one job alone leaves most of the GPU idle); all present at the
+        # start, served with 4 slots and with one, 10 iterations each
+        mixes = {
+            "small_jobs": (configs.small_instances(configs.SEED + 3, args.serving_small_jobs),
+                           "NA ~ U{64..160}, NE ~ U{200..320}, Nw ~ U{10..20}, Nkz = Nqz = 5"),
+            "tiny_jobs": (configs.tiny_instances(configs.SEED + 5, args.serving_small_jobs),
+                          "NA ~ U{8..16}, NE ~ U{30..60}, Nw ~ U{4..10}, Nkz = Nqz = 3"),
+        }
+        for key, (sp, sizes) in mixes.items():
+            # untimed warm-up over the first jobs (plans, allocator, first launches)
+            serving.Server(budget_bytes=200e9, slots=4, prec=sse.BF16X3, tol=1e-5).run(
+                serving.make_jobs(sp[:8], rate=1e9, seed=configs.SEED + 4, iterations=2))
+            mix = {}
+            for slots in (4, 1):
+                js = serving.make_jobs(sp, rate=1e9, seed=configs.SEED + 3)
+                r = serving.Server(budget_bytes=200e9, slots=slots, prec=sse.BF16X3,
+                                   tol=1e-5).run(js)
+                mix[slots] = serving.summarize(r)
+                log(f"{key}, {slots} slot(s): {mix[slots]['makespan_s']:.3f} s, "
+                    f"{mix[slots]['tflops']:.2f} TFLOP/s")
+            out[key] = {
+                "jobs": len(sp), "iterations_per_job": 10, "sizes": sizes,
+                "concurrent_4_slots": mix[4], "serial_1_slot": mix[1],
+                "speedup_vs_serial_resident": round(mix[4]["tflops"] / mix[1]["tflops"], 2)}
     return out
 
 
@@ -536,7 +583,7 @@ def main():
         progress(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
         torch.cuda.empty_cache()
-    if args.only in ("pi", "ablation", "aux"):
+    if args.only in ("pi", "ablation", "aux", "serving", "batch"):
         # one section alone (profiling runs); the ablation compares with the
         # headline, so that case times one binary64 step first
         out = {}
@@ -544,6 +591,10 @@ def main():
             out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, progress)
         elif args.only == "aux":
             out["aux"] = aux_section(args, torch, sse, prob, progress)
+        elif args.only == "serving":
+            out["serving"] = serving_section(args, torch, sse, configs, progress)
+        elif args.only == "batch":
+            out["batch"] = batch_section(args, torch, sse, configs, DeviceProblem, progress)
         else:
             ht, _ = time_form(sse.FP64, False, False)
             out["ablation_paper_form"] = ablation_section(args, torch, sse, prob, seed,

@@ -97,3 +97,22 @@ def batch_instances(seed: int = SEED, n: int = 48):
         out.append(Problem(NA=int(rng.integers(64, 2049)), NB=4, Norb=10, Nkz=5, Nqz=5,
                            NE=int(rng.integers(200, 1501)), Nw=int(rng.integers(10, 41))))
     return out
+
+
+def small_instances(seed: int = SEED, n: int = 24):
+    """Small serving jobs that do not fill the GPU: NA ~ U{64..160}, NE ~ U{200..320},
+    Nw ~ U{10..20}, Norb = 10, NB = 4, Nkz = Nqz = 5 (seeded)."""
+    rng = np.random.default_rng(seed)
+    return [Problem(NA=int(rng.integers(64, 161)), NB=4, Norb=10, Nkz=5, Nqz=5,
+                    NE=int(rng.integers(200, 321)), Nw=int(rng.integers(10, 21)))
+            for _ in range(n)]
+
+
+def tiny_instances(seed: int = SEED, n: int = 48):
+    """Jobs with fewer output tiles than the GPU has compute units (one job alone
+    leaves most of the GPU idle): NA ~ U{8..16}, NE ~ U{30..60}, Nw ~ U{4..10},
+    Norb = 10, NB = 4, Nkz = Nqz = 3 (seeded)."""
+    rng = np.random.default_rng(seed)
+    return [Problem(NA=int(rng.integers(8, 17)), NB=4, Norb=10, Nkz=3, Nqz=3,
+                    NE=int(rng.integers(30, 61)), Nw=int(rng.integers(4, 11)))
+            for _ in range(n)]

@@ -119,8 +119,9 @@ size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int No
 // Geometry of the phonon kernel (sse_pi.hip): the most neighbours per
 // workgroup (up to 4) whose buffers leave room for a ring of the taps' rows,
 // then the taps, sorted by increasing shift, cut into chunks of at most 32
-// whose ring fits.  LDS per workgroup: ring R + 1 rows of NNp (the pairs padded
-// to an even count) complex128 values; Zb NNp rows of 16 ntn binary64 columns;
+// whose ring fits.  LDS per workgroup: ring R + 2 rows (a step's R rows, a
+// spare for the next step's top row, a zero row) of NNp (the pairs padded to an
+// even count) complex128 values; Zb NNp rows of 16 ntn binary64 columns;
 // per neighbour U (3 blocks) and Y (1 block) complex128 and dH (3 blocks) binary64.
 PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
 {
@@ -137,7 +138,7 @@ PiGeom pi_geometry(int Norb, int NB, const int32_t *w_shift, int Nw)
     }
     auto ntn_of = [](int nbw) { return (nbw * 9 * 2 + 15) / 16; };
     auto fixed_of = [&](int nbw) {
-        return NNp * 16 + NNp * 16 * ntn_of(nbw) * 8 + (size_t)nbw * NN * (3 * 16 + 16 + 3 * 8);
+        return 2 * NNp * 16 + NNp * 16 * ntn_of(nbw) * 8 + (size_t)nbw * NN * (3 * 16 + 16 + 3 * 8);
     };
     const size_t per_row = NNp * 16;
     const size_t budget = pik::kLdsBudgetOne;

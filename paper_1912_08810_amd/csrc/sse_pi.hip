@@ -23,13 +23,17 @@
 // every (k, e).  A = X rows, read from a ring of atom a's rows in LDS (a tap is
 // an offset into it); B = Zt in LDS, the complex product folded into the
 // operand's sign and part.  One workgroup (8 waves) per (atom a, momentum q,
-// group of nbw neighbours, tap chunk) walks k, then e one energy per step: per
-// step the nbw neighbours' blocks Y[k, e, f] are staged and sandwiched into Zt
-// on the vector units (two rounds of Norb-long dot products through LDS), the
-// ring advances one row, and the eight waves split the step's K range, each
-// holding every output tile in its matrix-core accumulators; the eight partial
-// sums are added in a fixed order at the end.  The next step's rows load into
-// registers while a step's MFMAs run.
+// group of nbw neighbours, tap chunk) walks k, then e one energy per step; the
+// eight waves split the step's K range, each holding every output tile in its
+// matrix-core accumulators, and the eight partial sums are added in a fixed
+// order at the end.  The nbw neighbours' blocks Y[k, e, f] are sandwiched into
+// Zt on the vector units in two rounds of Norb-long dot products through LDS,
+// pipelined over the energy steps: while the MFMAs of step e run, each wave
+// computes the second round of step e + 1 for exactly the Zt rows its own MFMAs
+// read (interleaved with them, so the vector and matrix units work together,
+// and no barrier guards Zt); the first round of step e + 2 follows between two
+// barriers.  The ring holds one row more than a step reads, so the next step's
+// top row is written while the MFMAs read the others.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +46,7 @@ namespace {
 
 constexpr int kBlock = pik::kBlock;
 constexpr int kYP = 2;  // staged Y elements per thread and step (nbw NN <= 1024)
+constexpr int kS2Terms = 2;  // second-round m terms per MFMA step of the interleave
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Logical workgroup of physical workgroup `bid`: workgroups are dispatched
@@ -99,39 +104,56 @@ __device__ __forceinline__ void sandwich_first(const SandwichTasks &T, const dou
 // Second round: Zt_bij[n][p] = sum_m dH_bi[n][m] U[b][j][p][m] into the column
 // pair 2 (9 b + 3 i + j) + (re, im) of row c = n Norb + p of Zb (the orbital pair
 // of X it multiplies); a task is one (c, b) for all nine (i, j), sharing the
-// loads of the three dH rows and the three U rows.
-__device__ __forceinline__ void sandwich_second(const SandwichTasks &T, const double *dHs,
+// loads of the three dH rows and the three U rows.  The rows of Zb a wave
+// computes are the rows its own MFMA steps read, so Zb needs no barrier: one
+// m term of task u is added into (zr, zi) per call.
+__device__ __forceinline__ void sandwich_second_term(const SandwichTasks &T, int u, int m,
+                                                     const double *dHs, const double2 *Us,
+                                                     int NN, double (&zr)[kNF],
+                                                     double (&zi)[kNF])
+{
+    const double *h = dHs + T.h2[u];
+    const double2 *us = Us + T.u2[u];
+    double hi[3];
+    double2 uj[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        hi[t] = h[t * NN + m];
+        uj[t] = us[t * NN + m];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zr[3 * i + j] = fma(hi[i], uj[j].x, zr[3 * i + j]);
+            zi[3 * i + j] = fma(hi[i], uj[j].y, zi[3 * i + j]);
+        }
+}
+
+__device__ __forceinline__ void sandwich_second_store(const SandwichTasks &T, int u, double *Zb,
+                                                      const double (&zr)[kNF],
+                                                      const double (&zi)[kNF])
+{
+    if (T.o2[u] < 0)
+        return;
+    double2 *out = reinterpret_cast<double2 *>(Zb + T.o2[u]);
+#pragma unroll
+    for (int x = 0; x < kNF; ++x)
+        out[x] = make_double2(zr[x], zi[x]);
+}
+
+// Task u of the second round in full (every m term, then the store).
+__device__ __forceinline__ void sandwich_second(const SandwichTasks &T, int u, const double *dHs,
                                                 const double2 *Us, double *Zb, int NN, int No)
 {
-    for (int u = 0; u < T.n2; ++u) {
-        const double *h = dHs + T.h2[u];
-        const double2 *us = Us + T.u2[u];
-        double zr[kNF], zi[kNF];
+    double zr[kNF], zi[kNF];
 #pragma unroll
-        for (int x = 0; x < kNF; ++x)
-            zr[x] = zi[x] = 0.0;
+    for (int x = 0; x < kNF; ++x)
+        zr[x] = zi[x] = 0.0;
 #pragma unroll 1
-        for (int m = 0; m < No; ++m) {
-            double hi[3];
-            double2 uj[3];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                hi[t] = h[t * NN + m];
-                uj[t] = us[t * NN + m];
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    zr[3 * i + j] = fma(hi[i], uj[j].x, zr[3 * i + j]);
-                    zi[3 * i + j] = fma(hi[i], uj[j].y, zi[3 * i + j]);
-                }
-        }
-        double2 *out = reinterpret_cast<double2 *>(Zb + T.o2[u]);
-#pragma unroll
-        for (int x = 0; x < kNF; ++x)
-            out[x] = make_double2(zr[x], zi[x]);
-    }
+    for (int m = 0; m < No; ++m)
+        sandwich_second_term(T, u, m, dHs, Us, NN, zr, zi);
+    sandwich_second_store(T, u, Zb, zr, zi);
 }
 
 template <int MT, int NTN>
@@ -141,8 +163,11 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
     constexpr int ZC = 16 * NTN;                  // Zb row: 2 (b, i, j) columns, padded
     const int NN = p.NN, No = p.Norb, R = p.R, nbw = p.nbw;
     const int NNp = NN + (NN & 1);                // orbital pairs padded to an even count
-    double2 *ring = lds;                          // [R + 1][NNp]; row R and pair NN are zero
-    double *Zb = reinterpret_cast<double *>(ring + (size_t)(R + 1) * NNp);  // [NNp][ZC]
+    // ring slots: the R rows a step reads plus one, so that the next step's top
+    // row can be written while a step's MFMAs read the others
+    const int RS = R + 1;
+    double2 *ring = lds;                          // [RS + 1][NNp]; row RS and pair NN are zero
+    double *Zb = reinterpret_cast<double *>(ring + (size_t)(RS + 1) * NNp);  // [NNp][ZC]
     double2 *Us = reinterpret_cast<double2 *>(Zb + (size_t)NNp * ZC);     // [nbw 3][NN]
     double2 *Ys = Us + (size_t)nbw * 3 * NN;      // [nbw][NN]
     double *dHs = reinterpret_cast<double *>(Ys + (size_t)nbw * NN);  // [nbw 3][NN]
@@ -165,7 +190,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         dHs[x] = b < nbv ? p.dH[((size_t)a * p.NB + b0) * 3 * NN + x] : 0.0;
     }
     // zero once: the ring's zero row and padding pair, Zb's padding row and columns
-    for (int x = tid; x < (R + 1) * NNp; x += kBlock)
+    for (int x = tid; x < (RS + 1) * NNp; x += kBlock)
         ring[x] = make_double2(0.0, 0.0);
     for (int x = tid; x < NNp * ZC; x += kBlock)
         Zb[x] = 0.0;
@@ -186,14 +211,20 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
             T.ys[u] = o;
             T.yg[u] = (f >= 0 && f < p.NA) ? f * NN + rem : -1;
             T.ny = u + 1;
-            // round 2: o = (c, b)
-            const int c = o / nbw, b2 = o - c * nbw, n = c / No, r2 = c - n * No;
-            T.h2[u] = b2 * 3 * NN + n * No;
-            T.u2[u] = b2 * 3 * NN + r2 * No;
-            T.o2[u] = c * ZC + 2 * kNF * b2;
-            T.n2 = u + 1;
         }
+        // round 2: task t = lane + 64 u of this wave is (row i / nbw of the wave's
+        // rows c = 16 (i / 2) + 2 wave + i % 2, neighbour i % nbw); lanes past the
+        // wave's tasks compute on row 0 and store nothing
+        const int t = lane + 64 * u, ri = t / nbw, b2 = t - ri * nbw;
+        const int c = 16 * (ri >> 1) + 2 * wave + (ri & 1);
+        const bool ok = c < NN;
+        const int n = ok ? c / No : 0, r2 = ok ? c - n * No : 0;
+        T.h2[u] = b2 * 3 * NN + n * No;
+        T.u2[u] = b2 * 3 * NN + r2 * No;
+        T.o2[u] = ok ? c * ZC + 2 * kNF * b2 : -1;
     }
+    // tasks of round 2 per lane: 2 where some lane of the wave has a second one
+    T.n2 = __ballot(T.o2[1] >= 0) != 0 ? 2 : 1;
 
     // per lane: its tap row in each row tile, its K' slot, its columns
     const int kq = lane >> 4, xpart = kq & 1, chalf = kq >> 1;
@@ -233,10 +264,10 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         const double2 *Xk = p.X + ((size_t)kx * p.NE * p.NA + a) * NN;
         const double2 *Yk = p.Y + (size_t)k * p.NE * row_stride;
         __syncthreads();  // the previous k's last step is done with the ring, Us and Ys
-        // ring rows s_lo .. s_hi - 1 (step 0's rows but its top one); Y of step 0
-        for (int x = tid; x < (s_hi - s_lo) * NN; x += kBlock) {
+        // ring rows s_lo .. s_hi (step 0's rows); Y of step 0
+        for (int x = tid; x < (s_hi - s_lo + 1) * NN; x += kBlock) {
             const int row = s_lo + x / NN, c = x % NN;
-            ring[ring_slot(row, R) * NNp + c] =
+            ring[ring_slot(row, RS) * NNp + c] =
                 (row >= 0 && row < p.NE) ? Xk[(size_t)row * row_stride + c] : zero;
         }
         double2 yv[kYP], xv = zero;  // rows in flight: Y of a later step, the ring's next top row
@@ -250,48 +281,48 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
                     yv[u] = Yk[row_stride + T.yg[u]];
             }
         }
-        if (tid < NN && s_hi >= 0 && s_hi < p.NE)
-            xv = Xk[(size_t)s_hi * row_stride + tid];
+        if (tid < NN && 1 + s_hi >= 0 && 1 + s_hi < p.NE)
+            xv = Xk[(size_t)(1 + s_hi) * row_stride + tid];
         __syncthreads();
-        sandwich_first(T, dHs, Ys, Us, NN, No);
+        sandwich_first(T, dHs, Ys, Us, NN, No);   // U of step 0
         __syncthreads();
-        for (int es = 0;; ++es) {
-            // ---- phase B: second sandwich round of step es; the ring's top row
-            // for step es and Y of step es + 1 go to LDS; the next rows load
-            if (es < p.NE) {
-                sandwich_second(T, dHs, Us, Zb, NN, No);
-                if (tid < NN) {
-                    ring[ring_slot(es + s_hi, R) * NNp + tid] = xv;
-                    xv = zero;
-                    const int row = es + 1 + s_hi;
-                    if (row >= 0 && row < p.NE)
-                        xv = Xk[(size_t)row * row_stride + tid];
-                }
+        // Zt of step 0 (each wave its own rows); Y of step 1 to LDS
+        for (int u = 0; u < T.n2; ++u)
+            sandwich_second(T, u, dHs, Us, Zb, NN, No);
 #pragma unroll
-                for (int u = 0; u < kYP; ++u) {
-                    if (u < T.ny) {
-                        if (es + 1 < p.NE)
-                            Ys[T.ys[u]] = yv[u];
-                        yv[u] = zero;
-                        if (T.yg[u] >= 0 && es + 2 < p.NE)
-                            yv[u] = Yk[(size_t)(es + 2) * row_stride + T.yg[u]];
-                    }
-                }
+        for (int u = 0; u < kYP; ++u) {
+            if (u < T.ny) {
+                if (1 < p.NE)
+                    Ys[T.ys[u]] = yv[u];
+                yv[u] = zero;
+                if (T.yg[u] >= 0 && 2 < p.NE)
+                    yv[u] = Yk[(size_t)2 * row_stride + T.yg[u]];
             }
-            __syncthreads();
-            if (es >= p.NE)
-                break;
+        }
+        __syncthreads();
+        if (1 < p.NE)
+            sandwich_first(T, dHs, Ys, Us, NN, No);   // U of step 1
+        __syncthreads();
+        for (int es = 0; es < p.NE; ++es) {
             // ---- phase A: the MFMAs of step es (this wave's share of the orbital
-            // pairs; the other wave on the SIMD covers the operand loads), then the
-            // first sandwich round of es + 1
+            // pairs), with the second sandwich round of step es + 1 for the Zb rows
+            // those MFMAs read interleaved (the vector units work while the matrix
+            // cores run); the ring's top row of step es + 1 and Y of step es + 2 go
+            // to LDS, the next rows load
+            const bool next = es + 1 < p.NE;
             int ia[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                ia[mt] = ((tap_ok[mt] ? ring_slot(es + tap_s[mt], R) : R) * NNp +
+                ia[mt] = ((tap_ok[mt] ? ring_slot(es + tap_s[mt], RS) : RS) * NNp +
                           2 * wave + chalf) * 2 + xpart;
             int ib = (2 * wave + chalf) * ZC;
             constexpr int da = 4 * pik::kWaves;   // doubles between a lane's A operands
             const int db = 2 * pik::kWaves * ZC;
+            double zr[kNF], zi[kNF];
+#pragma unroll
+            for (int x = 0; x < kNF; ++x)
+                zr[x] = zi[x] = 0.0;
+            int m2 = 0;
             for (int s = wave; s < nks; s += pik::kWaves) {
                 double av[MT], bv[NTN];
 #pragma unroll
@@ -311,10 +342,47 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
                 for (int mt = 0; mt < MT; ++mt)
                     ia[mt] += da;
                 ib += db;
+                if (next) {
+#pragma unroll
+                    for (int v = 0; v < kS2Terms; ++v)
+                        if (m2 + v < No)
+                            sandwich_second_term(T, 0, m2 + v, dHs, Us, NN, zr, zi);
+                    m2 += kS2Terms;
+                }
             }
-            if (es + 1 < p.NE)
-                sandwich_first(T, dHs, Ys, Us, NN, No);
+            if (next) {
+                // this wave's MFMA reads of step es are issued: its Zb rows take step
+                // es + 1 (LDS operations of a wave complete in order)
+#pragma unroll 1
+                for (; m2 < No; ++m2)
+                    sandwich_second_term(T, 0, m2, dHs, Us, NN, zr, zi);
+                sandwich_second_store(T, 0, Zb, zr, zi);
+                if (T.n2 > 1)
+                    sandwich_second(T, 1, dHs, Us, Zb, NN, No);
+                if (tid < NN) {
+                    ring[ring_slot(es + 1 + s_hi, RS) * NNp + tid] = xv;
+                    xv = zero;
+                    const int row = es + 2 + s_hi;
+                    if (row >= 0 && row < p.NE)
+                        xv = Xk[(size_t)row * row_stride + tid];
+                }
+#pragma unroll
+                for (int u = 0; u < kYP; ++u) {
+                    if (u < T.ny) {
+                        if (es + 2 < p.NE)
+                            Ys[T.ys[u]] = yv[u];
+                        yv[u] = zero;
+                        if (T.yg[u] >= 0 && es + 3 < p.NE)
+                            yv[u] = Yk[(size_t)(es + 3) * row_stride + T.yg[u]];
+                    }
+                }
+            }
             __syncthreads();
+            // ---- phase B: the first sandwich round of step es + 2
+            if (es + 2 < p.NE) {
+                sandwich_first(T, dHs, Ys, Us, NN, No);
+                __syncthreads();
+            }
         }
     }
 

@@ -38,13 +38,16 @@ def parse():
                     help="precision forms timed after the binary64 headline ('' = none); "
                          "fp64c64 = binary64 arithmetic on complex64 storage; fp64ah = "
                          "binary64 with the anti-Hermitian D~ mode (half the tap work)")
+    ap.add_argument("--shard-gpus", type=int, default=8,
+                    help="time one GPU's energy shard of the device-scale problem split over "
+                         "this many GPUs (0 = skip)")
     ap.add_argument("--aux-steps", type=int, default=5,
                     help="timed steps of the D -> D~ and retarded passes at device scale "
                          "(0 = skip)")
     ap.add_argument("--only", default="",
                     help="time only this part, e.g. for profiling: a precision form (fp64, "
                          "fp32, bf16x3, fp64c64, fp64ah) or a section (pi, ablation, aux, "
-                         "serving, batch)")
+                         "serving, batch, shard)")
     ap.add_argument("--pi-steps", type=int, default=2,
                     help="timed steps of the phonon self-energy (Eqs. (4)-(5)) at device "
                          "scale, both components (0 = skip)")
@@ -251,6 +254,47 @@ def ablation_section(args, torch, sse, prob, seed, DeviceProblem, log, headline_
             "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
                          "kernel": "k_abl_gemm (+ k_abl_dhg, k_abl_dhd)"}}
+
+
+def shard_section(args, torch, sse, prob, seed, DeviceProblem, log):
+    """One GPU's share of the device-scale problem split over args.shard_gpus GPUs
+    by energy (the paper's energy decomposition, Sec. 4.1): the shard's NE / n
+    output energies plus the halo of shift-spread rows it reads, binary64, both
+    components, every atom and momentum on the GPU.  The halo rows' own outputs
+    are computed too (the library computes every energy of its G), so the timed
+    work is NE / n + spread energies per component."""
+    import dataclasses
+    s = prob.shifts()
+    spread = int(s.max() - s.min())
+    ne = -(-prob.NE // args.shard_gpus) + spread
+    sp = dataclasses.replace(prob, NE=ne)
+    dp = DeviceProblem(sp, seed, ncomp=2)
+    desc = sse.make_desc(sp.NA, sp.NB, sp.Norb, sp.Nkz, sp.Nqz, sp.NE, sp.Nw, ncomp=2,
+                         prec=sse.FP64)
+    plan = sse.sse_plan(desc, sp.shifts())
+    ws = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sse.sse_compute(plan, dp.neigh, dp.dH, dp.G, dp.D, dp.Sigma, ws, stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    t = statistics.median(times)
+    out_flops = 2 * prob.flops() / args.shard_gpus
+    log(f"shard of {args.shard_gpus}: NE {ne} ({prob.NE // args.shard_gpus} + halo {spread}), "
+        f"{t * 1e3:.1f} ms/step")
+    del dp, ws
+    torch.cuda.empty_cache()
+    return {"gpus": args.shard_gpus, "NE_computed": ne, "halo_energies": spread,
+            "ms_per_step": round(t * 1e3, 3),
+            "output_tflops": round(out_flops / t / 1e12, 3),
+            "computed_tflops": round(2 * sp.flops() / t / 1e12, 3),
+            "note": "binary64, both components; energies of one shard plus its halo"}
 
 
 def aux_section(args, torch, sse, prob, log):
@@ -583,7 +627,7 @@ def main():
         progress(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
         torch.cuda.empty_cache()
-    if args.only in ("pi", "ablation", "aux", "serving", "batch"):
+    if args.only in ("pi", "ablation", "aux", "serving", "batch", "shard"):
         # one section alone (profiling runs); the ablation compares with the
         # headline, so that case times one binary64 step first
         out = {}
@@ -591,6 +635,8 @@ def main():
             out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, progress)
         elif args.only == "aux":
             out["aux"] = aux_section(args, torch, sse, prob, progress)
+        elif args.only == "shard":
+            out["shard"] = shard_section(args, torch, sse, prob, seed, DeviceProblem, progress)
         elif args.only == "serving":
             out["serving"] = serving_section(args, torch, sse, configs, progress)
         elif args.only == "batch":
@@ -688,6 +734,8 @@ def main():
         args.batch, args.serving_jobs, args.pi_steps = "", 0, 0
     if args.pi_steps > 0:
         out["phonon"] = pi_section(args, torch, sse, prob, seed, DeviceProblem, log)
+    if args.shard_gpus > 0 and not args.only:
+        out["shard"] = shard_section(args, torch, sse, prob, seed, DeviceProblem, log)
     if args.aux_steps > 0 and not args.only:
         out["aux"] = aux_section(args, torch, sse, prob, log)
     if args.ablation_steps > 0 and not args.only:

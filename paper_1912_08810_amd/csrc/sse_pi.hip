@@ -45,7 +45,6 @@ namespace sse {
 namespace {
 
 constexpr int kBlock = pik::kBlock;
-constexpr int kYP = 2;  // staged Y elements per thread and step (nbw NN <= 1024)
 constexpr int kS2Terms = 2;  // second-round m terms per MFMA step of the interleave
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -69,6 +68,9 @@ __device__ __forceinline__ int ring_slot(int row, int R)
 // Per-thread offsets of the two sandwich rounds and of the Y staging; a
 // thread's tasks are the same at every step (at most two each, since
 // nbw Norb^2 <= 1024 = 2 kBlock), so their index arithmetic is done once.
+// Every loop over a thread's tasks runs over the constant bound 2 with a
+// guard: an array indexed by a run-time value would be placed in private
+// (scratch) memory and reloaded from it at every step.
 struct SandwichTasks {
     int n1, n2, ny;                 // tasks of round 1, round 2, staged Y elements
     int h1[2], y1[2], o1[2];        // round 1: dH row, Y column, U output
@@ -81,7 +83,10 @@ struct SandwichTasks {
 __device__ __forceinline__ void sandwich_first(const SandwichTasks &T, const double *dHs,
                                                const double2 *Ys, double2 *Us, int NN, int No)
 {
-    for (int u = 0; u < T.n1; ++u) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (u >= T.n1)
+            break;
         const double *h = dHs + T.h1[u];
         const double2 *y = Ys + T.y1[u];
         double ur[3] = {0.0, 0.0, 0.0}, ui[3] = {0.0, 0.0, 0.0};
@@ -255,7 +260,6 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
             acc[mt][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
 
     const size_t row_stride = (size_t)p.NA * NN;  // one energy step of G
-    const double2 zero = make_double2(0.0, 0.0);
     const int nks = NNp >> 1;                     // MFMA steps (two orbital pairs each) per energy
     const double *ringd = reinterpret_cast<const double *>(ring);
 
@@ -267,38 +271,46 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         // ring rows s_lo .. s_hi (step 0's rows); Y of step 0
         for (int x = tid; x < (s_hi - s_lo + 1) * NN; x += kBlock) {
             const int row = s_lo + x / NN, c = x % NN;
-            ring[ring_slot(row, RS) * NNp + c] =
-                (row >= 0 && row < p.NE) ? Xk[(size_t)row * row_stride + c] : zero;
+            ring[ring_slot(row, RS) * NNp + c] = (row >= 0 && row < p.NE)
+                                                      ? Xk[(size_t)row * row_stride + c]
+                                                      : make_double2(0.0, 0.0);
         }
-        double2 yv[kYP], xv = zero;  // rows in flight: Y of a later step, the ring's next top row
-#pragma unroll
-        for (int u = 0; u < kYP; ++u) {
-            yv[u] = zero;
-            if (u < T.ny) {
-                const bool ok = T.yg[u] >= 0;
-                Ys[T.ys[u]] = ok ? Yk[T.yg[u]] : zero;
-                if (ok && 1 < p.NE)
-                    yv[u] = Yk[row_stride + T.yg[u]];
-            }
-        }
-        if (tid < NN && 1 + s_hi >= 0 && 1 + s_hi < p.NE)
-            xv = Xk[(size_t)(1 + s_hi) * row_stride + tid];
+        // Rows in flight: Y elements of a later step (two scalars: an array
+        // element written under a branch put the array in private memory) and the
+        // ring's next top row.  Every step first stores the rows in flight to LDS
+        // and only then requests the next ones, so that no LDS store waits for a
+        // global load issued in the same step (the vector-memory counter is
+        // waited in order).
+        auto load_y = [&](int u, int e) {
+            return (u < T.ny && T.yg[u] >= 0 && e < p.NE)
+                       ? Yk[(size_t)e * row_stride + T.yg[u]]
+                       : make_double2(0.0, 0.0);
+        };
+        auto put_y = [&](int u, double2 v) {
+            if (u < T.ny)
+                Ys[T.ys[u]] = v;
+        };
+        auto load_x = [&](int row) {
+            return (tid < NN && row >= 0 && row < p.NE) ? Xk[(size_t)row * row_stride + tid]
+                                                        : make_double2(0.0, 0.0);
+        };
+        put_y(0, load_y(0, 0));
+        put_y(1, load_y(1, 0));
+        double2 yv0 = load_y(0, 1), yv1 = load_y(1, 1), xv = load_x(1 + s_hi);
         __syncthreads();
         sandwich_first(T, dHs, Ys, Us, NN, No);   // U of step 0
         __syncthreads();
         // Zt of step 0 (each wave its own rows); Y of step 1 to LDS
-        for (int u = 0; u < T.n2; ++u)
-            sandwich_second(T, u, dHs, Us, Zb, NN, No);
 #pragma unroll
-        for (int u = 0; u < kYP; ++u) {
-            if (u < T.ny) {
-                if (1 < p.NE)
-                    Ys[T.ys[u]] = yv[u];
-                yv[u] = zero;
-                if (T.yg[u] >= 0 && 2 < p.NE)
-                    yv[u] = Yk[(size_t)2 * row_stride + T.yg[u]];
-            }
+        for (int u = 0; u < 2; ++u)
+            if (u < T.n2)
+                sandwich_second(T, u, dHs, Us, Zb, NN, No);
+        if (1 < p.NE) {
+            put_y(0, yv0);
+            put_y(1, yv1);
         }
+        yv0 = load_y(0, 2);
+        yv1 = load_y(1, 2);
         __syncthreads();
         if (1 < p.NE)
             sandwich_first(T, dHs, Ys, Us, NN, No);   // U of step 1
@@ -359,23 +371,15 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
                 sandwich_second_store(T, 0, Zb, zr, zi);
                 if (T.n2 > 1)
                     sandwich_second(T, 1, dHs, Us, Zb, NN, No);
-                if (tid < NN) {
+                if (tid < NN)
                     ring[ring_slot(es + 1 + s_hi, RS) * NNp + tid] = xv;
-                    xv = zero;
-                    const int row = es + 2 + s_hi;
-                    if (row >= 0 && row < p.NE)
-                        xv = Xk[(size_t)row * row_stride + tid];
+                if (es + 2 < p.NE) {
+                    put_y(0, yv0);
+                    put_y(1, yv1);
                 }
-#pragma unroll
-                for (int u = 0; u < kYP; ++u) {
-                    if (u < T.ny) {
-                        if (es + 2 < p.NE)
-                            Ys[T.ys[u]] = yv[u];
-                        yv[u] = zero;
-                        if (T.yg[u] >= 0 && es + 3 < p.NE)
-                            yv[u] = Yk[(size_t)(es + 3) * row_stride + T.yg[u]];
-                    }
-                }
+                xv = load_x(es + 2 + s_hi);
+                yv0 = load_y(0, es + 3);
+                yv1 = load_y(1, es + 3);
             }
             __syncthreads();
             // ---- phase B: the first sandwich round of step es + 2

@@ -90,7 +90,7 @@ __device__ __forceinline__ void sandwich_first(const SandwichTasks &T, const dou
         const double *h = dHs + T.h1[u];
         const double2 *y = Ys + T.y1[u];
         double ur[3] = {0.0, 0.0, 0.0}, ui[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
+#pragma unroll 5
         for (int r = 0; r < No; ++r) {
             const double2 v = y[r * No];
 #pragma unroll
@@ -202,10 +202,14 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
 
     SandwichTasks T;
     T.n1 = T.n2 = T.ny = 0;
+    // round-1 tasks dealt evenly over the eight waves (the two waves of a SIMD
+    // then carry the same number): wave w takes tasks [w per, (w + 1) per)
+    const int per_wave = (nbw * NN + pik::kWaves - 1) / pik::kWaves;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const int o = tid + u * kBlock;
-        if (o < nbw * NN) {
+        const int lo = lane + 64 * u;
+        const int o = wave * per_wave + lo;
+        if (lo < per_wave && o < nbw * NN) {
             // round 1 and Y staging: o = (b, p, m)
             const int b = o / NN, rem = o - b * NN, r0 = rem / No, m = rem - r0 * No;
             T.h1[u] = b * 3 * NN + r0 * No;

@@ -1,0 +1,94 @@
+"""Degenerate and extreme shapes of the electron self-energy (Eq. (3)) through
+the C ABI, in every precision, against the oracle on the same stored inputs:
+
+* one atom that is its own only neighbour, one orbital, one momentum, one
+  energy and one frequency (the smallest problem the ABI accepts);
+* shifts at the edge of the energy grid (|s| = NE - 1: each such tap meets one
+  in-range row), and a shift of NE refused at plan time;
+* the largest frequency count the ABI accepts (128 taps);
+* one GPU's share of the device-scale problem split over 8 GPUs by energy
+  (125 energies plus the 29 halo rows, binary64), on sampled blocks.
+
+Bars (relative Frobenius error per component): binary64 1e-12, fp32 products
+1e-5, bf16 hi/lo products 1e-3, binary64 on complex64 storage 1e-7 (its store
+rounds to complex64).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1912_08810_amd import configs
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+PRECS = [0, 1, 2, 3]
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-3, 3: 1e-7}
+
+
+def _dp(prob, seed, prec, neigh=None, ncomp=2):
+    return gu.DeviceProblem(prob, seed, ncomp=ncomp, fp32=prec != 0, neigh=neigh)
+
+
+def _check(dp, prec):
+    for c in range(dp.ncomp):
+        got = dp.sigma_host(c)
+        want = gu.oracle_full(dp, c)
+        err = gu.rel_fro(got, want)
+        print(f"  prec={prec} comp {c}: rel_fro={err:.3e}", flush=True)
+        assert err <= TOL[prec], (prec, c, err)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_atom_own_neighbour_one_of_everything(prec):
+    prob = configs.Problem(NA=1, NB=1, Norb=1, Nkz=1, Nqz=1, NE=1, Nw=1, shift=(0,))
+    dp = _dp(prob, 41, prec, neigh=np.zeros((1, 1), dtype=np.int32))
+    assert gu.run_sse(dp, prec=prec) == 0
+    _check(dp, prec)
+    assert np.abs(dp.sigma_host(0)).max() > 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_shifts_at_the_edge_of_the_energy_grid(prec):
+    # |s| = NE - 1: each such tap reads one in-range energy row for one output
+    # energy and the zero padding for the others
+    prob = configs.Problem(NA=5, NB=2, Norb=4, Nkz=2, Nqz=2, NE=4, Nw=6,
+                           shift=(3, -3, 3, -3, 2, 0))
+    dp = _dp(prob, 43, prec)
+    assert gu.run_sse(dp, prec=prec) == 0
+    for c in range(dp.ncomp):
+        assert not np.isnan(dp.sigma_host(c)).any()
+    _check(dp, prec)
+
+
+def test_shift_not_below_the_energy_count_is_refused():
+    from paper_1912_08810_amd import sse
+    prob = configs.Problem(NA=5, NB=2, Norb=4, Nkz=2, Nqz=2, NE=3, Nw=2, shift=(1, 3))
+    desc = sse.make_desc(prob.NA, prob.NB, prob.Norb, prob.Nkz, prob.Nqz, prob.NE, prob.Nw)
+    with pytest.raises(sse.SSEError) as ei:
+        sse.sse_plan(desc, prob.shifts())
+    assert ei.value.status == sse.ERR_SHAPE
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_frequency_count(prec):
+    prob = configs.Problem(NA=3, NB=2, Norb=4, Nkz=2, Nqz=2, NE=160, Nw=128)
+    dp = _dp(prob, 47, prec)
+    assert gu.run_sse(dp, prec=prec) == 0
+    _check(dp, prec)
+
+
+def test_device_scale_energy_shard_sampled():
+    prob = configs.DEVICE
+    s = prob.shifts()
+    ne = -(-prob.NE // 8) + int(s.max() - s.min())
+    shard = dataclasses.replace(prob, NE=ne)
+    dp = gu.DeviceProblem(shard, configs.SEED + 8, ncomp=1)
+    assert gu.run_sse(dp, prec=0) == 0
+    blocks = gu.sample_blocks(shard, 31, n_e=12, n_a=6)
+    got = dp.device_blocks(0, blocks)
+    want = gu.oracle_blocks(dp, 0, blocks)
+    err, emax = gu.rel_fro(got, want), gu.max_elem_rel(got, want)
+    print(f"  shard NE={ne}: {len(blocks)} blocks rel_fro={err:.3e} max_elem={emax:.3e}",
+          flush=True)
+    assert err <= TOL[0] and emax <= TOL[0]

@@ -29,3 +29,20 @@ def test_runtime_host_code_under_sanitizers(tmp_path):
                UBSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])
+
+
+def test_phonon_geometry_fits_the_kernel_layout(tmp_path):
+    """pi_geometry against the phonon kernel's LDS layout and task mapping over
+    orbital, neighbour and frequency counts and four shift-table shapes."""
+    exe = os.path.join(tmp_path, "pi_geometry_check")
+    cmd = ["g++", "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined",
+           "-fno-omit-frame-pointer", "-x", "c++", "-I", H, "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, os.path.join(CSRC, "sse_geometry.hip"),
+           os.path.join(H, "pi_geometry_check.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    print(r.stdout[-500:])
+    assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])

@@ -256,18 +256,51 @@ __device__ __forceinline__ void fp64_tile(const_ptr<Fp64Params> pp, const Tensor
                     if (t < t1)
                         step(dA, dB);
                 }
-                // complex64: one tap at a time, loads then one wait (its
-                // conversions need the registers a prefetch would take)
-                for (; t < t1; ++t) {
-                    const_ptr<T> dpa = Dq + (size_t)p.taps.w[t] * strideD;
-                    double2 da[kNF];
+                if constexpr (sizeof(T) != sizeof(double2)) {
+                    // complex64: the same pipeline, the D~ in flight held as
+                    // complex64 (scalar registers) and promoted where it is used
+                    T fA[kNF], fB[kNF];
+                    int sh = p.tws[2 * t + 1], wn = p.tws[2 * t + 2];
+                    {
+                        const_ptr<T> dp = Dq + (size_t)p.tws[2 * t] * strideD;
 #pragma unroll
-                    for (int x = 0; x < kNF; ++x)
-                        da[x] = to_d2(dpa[x]);
-                    const double2 *wpa = lds + tid + (smax - p.taps.s[t]) * NN;
+                        for (int x = 0; x < kNF; ++x)
+                            fA[x] = dp[x];
+                    }
+                    auto step = [&](T(&cur)[kNF], T(&nxt)[kNF]) {
+                        const double2 *wp = lds + tid + (smax - sh) * NN;
+                        double2 g[kR];
 #pragma unroll
-                    for (int r = 0; r < kR; ++r)
-                        tap_update<AH>(ar[r], ai[r], da, wpa[r * kBlock]);
+                        for (int r = 0; r < kR; ++r)
+                            g[r] = wp[r * kBlock];
+                        const int sh2 = p.tws[2 * t + 3], wn2 = p.tws[2 * t + 4];
+                        __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        {
+                            const_ptr<T> dp = Dq + (size_t)wn * strideD;
+#pragma unroll
+                            for (int x = 0; x < kNF; ++x)
+                                nxt[x] = dp[x];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        double2 d[kNF];
+#pragma unroll
+                        for (int x = 0; x < kNF; ++x)
+                            d[x] = to_d2(cur[x]);
+#pragma unroll
+                        for (int r = 0; r < kR; ++r)
+                            tap_update<AH>(ar[r], ai[r], d, g[r]);
+                        sh = sh2;
+                        wn = wn2;
+                        ++t;
+                    };
+                    while (t + 1 < t1) {
+                        step(fA, fB);
+                        step(fB, fA);
+                    }
+                    if (t < t1)
+                        step(fA, fB);
                 }
             }
         }

@@ -98,7 +98,10 @@ __global__ void k_abl_dhd(AblParams p, int a0, int nat)
 // the window of M_i rows and the stacked N_i[q, :] are staged into LDS in
 // ready-made form: the window with a zero row (the padding rows' operand), N_i
 // as binary64 rows of 32 columns (n, re/im) with zero padding, so an operand is
-// one 8-byte LDS read and, for the imaginary part of M, a sign flip.
+// one 8-byte LDS read and, for the imaginary part of M, a sign flip.  A table of
+// each K entry's offset into the window (built once) replaces the per-step
+// (w, l) arithmetic, so the operands of the next K step can be read while the
+// MFMAs of the current one run.
 __global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int a0)
 {
     extern __shared__ double2 lds[];
@@ -106,10 +109,12 @@ __global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int
     const int NN = p.NN, No = p.Norb, TE = p.TE;
     const int nrow = p.win_rows;                   // TE + shift spread
     double2 *win = lds;                            // [nrow + 1][NN]: M_i rows, then a zero row
-    double *nb = reinterpret_cast<double *>(win + (size_t)(nrow + 1) * NN);  // [Kp][ZC]
+    double *nb = reinterpret_cast<double *>(win + (size_t)(nrow + 1) * NN);  // [Kp + 2][ZC]
     const int Kcount = p.Nw * No;                  // complex K entries (w, l)
     const int Kp = Kcount + (Kcount & 1);
-    int *rowoff = reinterpret_cast<int *>(nb + (size_t)Kp * ZC);  // [Nw]: (smax - s_w) NN
+    // A offset (doubles, from a lane's row base) of complex K entry (w, l):
+    // ((smax - s_w) NN + l) 2; entries past Kcount are 0 (their N rows are zero)
+    int *aoff = reinterpret_cast<int *>(nb + (size_t)(Kp + 2) * ZC);  // [Kp + 4]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     int64_t L = blockIdx.x;
@@ -120,11 +125,13 @@ __global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int
     const int a = a0 + al;
     const int e0 = et * TE;
     const int te = min(TE, p.NE - e0);
-    for (int w = tid; w < p.Nw; w += pik::kAblBlock)
-        rowoff[w] = (p.smax - p.shift[w]) * NN;
+    for (int x = tid; x < Kp + 4; x += pik::kAblBlock) {
+        const int w = x / No, l = x - w * No;
+        aoff[x] = x < Kcount ? ((p.smax - p.shift[w]) * NN + l) * 2 : 0;
+    }
     for (int x = tid; x < NN; x += pik::kAblBlock)
         win[(size_t)nrow * NN + x] = make_double2(0.0, 0.0);
-    for (int x = tid; x < Kp * ZC; x += pik::kAblBlock)
+    for (int x = tid; x < (Kp + 2) * ZC; x += pik::kAblBlock)
         nb[x] = 0.0;
 
     // this lane's A row (e, m), K' slot and B column
@@ -135,6 +142,7 @@ __global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int
     // A: M window element (row of e - s_w, m, l), part xpart; padding rows read the zero row
     const int abase = arow_ok ? (ae * NN + am * No) * 2 + xpart : nrow * NN * 2;
     const int arow_step = arow_ok ? 1 : 0;       // padding lanes stay on the zero row
+    const int *ao = aoff + chalf;                // this lane's K entries: ao[2 s]
     // B: x re reads (N re, N im) for the columns (re, im); x im reads (-N im, N re)
     int bsrc[pik::kAblNT];
     unsigned bsign[pik::kAblNT];
@@ -175,30 +183,35 @@ __global__ __launch_bounds__(pik::kAblBlock, 1) void k_abl_gemm(AblParams p, int
                     nb[kc * ZC + 2 * n + 1] = v.y;
                 }
                 __syncthreads();
-                // K loop: step s covers complex K entries 2 s and 2 s + 1 = (w, l)
-                int Kc = chalf, w = 0, l = Kc;
-                while (l >= No) {
-                    l -= No;
-                    ++w;
-                }
-                int ib = Kc * ZC;
+                // K loop: step s covers complex K entries 2 s and 2 s + 1 = (w, l).
+                // The operands of step s + 1 are read while the MFMAs of step s run
+                // (past the last step they come from the padding rows and entries)
+                int ib = chalf * ZC;
+                double a_cur = wind[abase + arow_step * ao[0]];
+                double b_cur[pik::kAblNT];
+#pragma unroll
+                for (int t = 0; t < pik::kAblNT; ++t)
+                    b_cur[t] = nb[ib + bsrc[t]];
+                int ao_nx = ao[2];
                 for (int s = 0; s < nks; ++s) {
-                    // the padding K entry (Kcount odd) reads a zero N row
-                    const int wc = w < p.Nw ? w : 0;
-                    const double av = wind[abase + arow_step * ((rowoff[wc] + l) * 2)];
+                    const int ao_nn = ao[2 * s + 4];
+                    const double a_n = wind[abase + arow_step * ao_nx];
+                    double b_n[pik::kAblNT];
+#pragma unroll
+                    for (int t = 0; t < pik::kAblNT; ++t)
+                        b_n[t] = nb[ib + 2 * ZC + bsrc[t]];
 #pragma unroll
                     for (int t = 0; t < pik::kAblNT; ++t) {
-                        const double x = nb[ib + bsrc[t]];
-                        const double bv = __hiloint2double(__double2hiint(x) ^ (int)bsign[t],
-                                                           __double2loint(x));
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                        const double bv = __hiloint2double(
+                            __double2hiint(b_cur[t]) ^ (int)bsign[t], __double2loint(b_cur[t]));
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur, bv, acc[t], 0, 0, 0);
                     }
+                    a_cur = a_n;
+#pragma unroll
+                    for (int t = 0; t < pik::kAblNT; ++t)
+                        b_cur[t] = b_n[t];
+                    ao_nx = ao_nn;
                     ib += 2 * ZC;
-                    l += 2;
-                    while (l >= No) {
-                        l -= No;
-                        ++w;
-                    }
                 }
             }
         }

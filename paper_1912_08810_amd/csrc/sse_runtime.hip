@@ -1037,8 +1037,8 @@ sse_status sse_ablation_compute(sse_plan_t plan, const int32_t *neigh, const dou
     p.alpha_re = d.alpha_re;
     p.alpha_im = d.alpha_im;
     const size_t kp = (size_t)d.Nw * d.Norb + ((size_t)d.Nw * d.Norb & 1);
-    const size_t lds = std::max((size_t)(p.win_rows + 1) * NN * 16 + kp * 16 * pik::kAblNT * 8 +
-                                    4 * (size_t)d.Nw,
+    const size_t lds = std::max((size_t)(p.win_rows + 1) * NN * 16 +
+                                    (kp + 2) * 16 * pik::kAblNT * 8 + 4 * (kp + 4),
                                 (size_t)pik::kAblRows * 16 * pik::kAblNT * 8);
     if (lds > pik::kLdsBudgetOne)
         return fail(SSE_ERR_UNSUPPORTED,

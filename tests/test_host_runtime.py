@@ -6,7 +6,8 @@ regression test for polling: a pending sse_poll must not make the next
 submission report a launch failure.  The persistent launchers' stand-ins run
 the kernels' tile-pull code for simulated workgroups in a scrambled order
 (grids of 1 to the plan's size, batches that leave work queues empty): every
-tile must come out exactly once."""
+tile must come out exactly once.  The two C oracles run under the same
+sanitizers (with OpenMP) through each of their paths."""
 import os
 import subprocess
 
@@ -43,6 +44,26 @@ def test_phonon_geometry_fits_the_kernel_layout(tmp_path):
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    print(r.stdout[-500:])
+    assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])
+
+
+def test_oracles_under_sanitizers(tmp_path):
+    """Both C oracles built with AddressSanitizer, UBSan and OpenMP, driven
+    through the full, block-list and stacked-block (gslot) paths and their
+    error returns; block-list and gslot results must equal the full
+    evaluation bit for bit."""
+    exe = os.path.join(tmp_path, "oracle_driver")
+    odir = os.path.join(ROOT, "oracle")
+    cmd = ["gcc", "-std=c11", "-g", "-O1", "-fopenmp", "-fsanitize=address,undefined",
+           "-fno-omit-frame-pointer", os.path.join(odir, "sse_oracle.c"),
+           os.path.join(odir, "pi_oracle.c"), os.path.join(H, "oracle_driver.c"), "-lm",
+           "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1", OMP_NUM_THREADS="3")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
     print(r.stdout[-500:])
     assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])

@@ -72,9 +72,9 @@ __device__ __forceinline__ int ring_slot(int row, int R)
 // guard: an array indexed by a run-time value would be placed in private
 // (scratch) memory and reloaded from it at every step.
 struct SandwichTasks {
-    int n1, n2, ny;                 // tasks of round 1, round 2, staged Y elements
-    int h1[2], y1[2], o1[2];        // round 1: dH row, Y column, U output
-    int h2[2], u2[2], o2[2];        // round 2: dH rows, U rows, Zb output (double index)
+    int n1, n2, ny;                 // tasks of the first and second rounds, staged Y elements
+    int h1[2], y1[2], o1[2];        // first round: dH row, Y column, U output
+    int h2[2], u2[2], o2[2];        // second round: dH rows, U rows, Zb output (double index)
     int ys[2], yg[2];               // Y staging: LDS slot, element offset in a G energy row (-1: zero)
 };
 
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
 
     SandwichTasks T;
     T.n1 = T.n2 = T.ny = 0;
-    // round-1 tasks dealt evenly over the eight waves (the two waves of a SIMD
+    // first-round tasks dealt evenly over the eight waves (the two waves of a SIMD
     // then carry the same number): wave w takes tasks [w per, (w + 1) per)
     const int per_wave = (nbw * NN + pik::kWaves - 1) / pik::kWaves;
 #pragma unroll
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         const int lo = lane + 64 * u;
         const int o = wave * per_wave + lo;
         if (lo < per_wave && o < nbw * NN) {
-            // round 1 and Y staging: o = (b, p, m)
+            // first round and Y staging: o = (b, p, m)
             const int b = o / NN, rem = o - b * NN, r0 = rem / No, m = rem - r0 * No;
             T.h1[u] = b * 3 * NN + r0 * No;
             T.y1[u] = b * NN + m;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
             T.yg[u] = (f >= 0 && f < p.NA) ? f * NN + rem : -1;
             T.ny = u + 1;
         }
-        // round 2: task t = lane + 64 u of this wave is (row i / nbw of the wave's
+        // second round: task t = lane + 64 u of this wave is (row i / nbw of the wave's
         // rows c = 16 (i / 2) + 2 wave + i % 2, neighbour i % nbw); lanes past the
         // wave's tasks compute on row 0 and store nothing
         const int t = lane + 64 * u, ri = t / nbw, b2 = t - ri * nbw;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_pi_mfma(const PiParams p)
         T.u2[u] = b2 * 3 * NN + r2 * No;
         T.o2[u] = ok ? c * ZC + 2 * kNF * b2 : -1;
     }
-    // tasks of round 2 per lane: 2 where some lane of the wave has a second one
+    // tasks of the second round per lane: 2 where some lane of the wave has a second one
     T.n2 = __ballot(T.o2[1] >= 0) != 0 ? 2 : 1;
 
     // per lane: its tap row in each row tile, its K' slot, its columns

@@ -72,18 +72,18 @@ int main()
                             g.ts[t] != s[g.tw[t]])
                             return fail("taps", Norb, NB, Nw, pattern);
                     }
-                    // first round: at most two tasks per thread, dealt over the waves
+                    // first sandwich round: at most two tasks per thread, dealt over the waves
                     const size_t per_wave = (g.nbw * NN + pik::kWaves - 1) / pik::kWaves;
                     if (per_wave > 128)
-                        return fail("round-1 tasks", Norb, NB, Nw, pattern);
-                    // second round: the rows a wave's MFMA steps read, times nbw
+                        return fail("first-round tasks", Norb, NB, Nw, pattern);
+                    // second sandwich round: the rows a wave's MFMA steps read, times nbw
                     for (int w = 0; w < pik::kWaves; ++w) {
                         size_t rows = 0;
                         for (size_t c = 0; c < NN; ++c)
                             if ((c >> 1) % pik::kWaves == (size_t)w)
                                 ++rows;
                         if (rows * g.nbw > 128)
-                            return fail("round-2 tasks", Norb, NB, Nw, pattern);
+                            return fail("second-round tasks", Norb, NB, Nw, pattern);
                     }
                 }
     std::printf("OK %ld geometries checked, %ld refused\n", checked, refused);

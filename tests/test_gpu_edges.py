@@ -5,7 +5,8 @@ the C ABI, in every precision, against the oracle on the same stored inputs:
   energy and one frequency (the smallest problem the ABI accepts);
 * shifts at the edge of the energy grid (|s| = NE - 1: each such tap meets one
   in-range row), and a shift of NE refused at plan time;
-* the largest frequency count the ABI accepts (128 taps);
+* the largest frequency count the ABI accepts (128 taps) and the largest
+  neighbour count (50: every other atom of a 51-atom system);
 * one GPU's share of the device-scale problem split over 8 GPUs by energy
   (125 energies plus the 29 halo rows, binary64), on sampled blocks.
 
@@ -74,6 +75,15 @@ def test_shift_not_below_the_energy_count_is_refused():
 def test_largest_frequency_count(prec):
     prob = configs.Problem(NA=3, NB=2, Norb=4, Nkz=2, Nqz=2, NE=160, Nw=128)
     dp = _dp(prob, 47, prec)
+    assert gu.run_sse(dp, prec=prec) == 0
+    _check(dp, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_neighbour_count(prec):
+    # NB = 50, the most the ABI accepts: every other atom is a neighbour
+    prob = configs.Problem(NA=51, NB=50, Norb=4, Nkz=2, Nqz=2, NE=6, Nw=3)
+    dp = _dp(prob, 49, prec)
     assert gu.run_sse(dp, prec=prec) == 0
     _check(dp, prec)
 

@@ -4,8 +4,9 @@ oracle, through the C ABI.
 Tolerance: relative Frobenius error <= 1e-12 per component (the binary64
 bar), and element-wise deviation <= 1e-12 of the largest |Pi| element.  Cases
 span the CPU-scale configuration, ragged and odd shapes (Norb 1..16, negative
-and unsorted shifts, more taps than one workgroup holds, Nqz < Nkz, a single
-energy), self and duplicate neighbours, a general prefactor, the
+and unsorted shifts, shifts at the edge of the energy grid, more taps than one
+workgroup holds, several neighbour groups, Nqz < Nkz, a single energy), self and
+duplicate neighbours, a general prefactor, the
 device-scale configuration on sampled blocks, and the error paths.
 """
 import numpy as np
@@ -44,7 +45,16 @@ def test_small_config_full_both_components():
     configs.Problem(NA=6, NB=2, Norb=3, Nkz=3, Nqz=2, NE=30, Nw=40, shift=tuple(range(-20, 20))),
     configs.Problem(NA=9, NB=4, Norb=10, Nkz=3, Nqz=3, NE=37, Nw=30),
     configs.Problem(NA=4, NB=3, Norb=7, Nkz=5, Nqz=5, NE=1, Nw=2, shift=(0, 0)),
-], ids=["odd", "norb1", "norb16", "two_chunks", "norb10_nw30", "one_energy"])
+    # two neighbour groups (4 + 2 neighbours per workgroup)
+    configs.Problem(NA=8, NB=6, Norb=4, Nkz=3, Nqz=2, NE=12, Nw=5),
+    # three neighbour groups (4 + 4 + 1) and shifts at the edge of the energy grid
+    configs.Problem(NA=11, NB=9, Norb=3, Nkz=2, Nqz=2, NE=10, Nw=3, shift=(9, -9, 0)),
+    # Norb 16 with a shift spread of 40: one neighbour per workgroup, three tap chunks
+    configs.Problem(NA=4, NB=3, Norb=16, Nkz=2, Nqz=2, NE=24, Nw=40, shift=tuple(range(-20, 20))),
+    # the largest neighbour count the ABI accepts (13 neighbour groups)
+    configs.Problem(NA=51, NB=50, Norb=3, Nkz=2, Nqz=2, NE=6, Nw=3),
+], ids=["odd", "norb1", "norb16", "two_chunks", "norb10_nw30", "one_energy", "nb6", "nb9_edges",
+        "norb16_wide", "nb50"])
 def test_shapes(prob):
     dp = gu.DeviceProblem(prob, 17, ncomp=2)
     st, Pi = gu.run_pi(dp)

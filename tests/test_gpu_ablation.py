@@ -35,7 +35,8 @@ def run_ablation(dp, atoms=None, alpha=1j):
     (configs.Problem(NA=9, NB=3, Norb=10, Nkz=4, Nqz=3, NE=29, Nw=7, shift=(3, 1, -2, 7, 5, 2, 4)), 4),
     (configs.Problem(NA=5, NB=2, Norb=1, Nkz=2, Nqz=2, NE=11, Nw=3), None),
     (configs.Problem(NA=4, NB=2, Norb=16, Nkz=2, Nqz=1, NE=9, Nw=2), None),
-], ids=["small", "small_chunks", "norb10_ragged", "norb1", "norb16"])
+    (configs.Problem(NA=51, NB=50, Norb=4, Nkz=2, Nqz=2, NE=6, Nw=3), 17),
+], ids=["small", "small_chunks", "norb10_ragged", "norb1", "norb16", "nb50"])
 def test_ablation_matches_oracle(prob, atoms):
     dp = gu.DeviceProblem(prob, 91, ncomp=2)
     assert run_ablation(dp, atoms) == 0

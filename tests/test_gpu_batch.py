@@ -94,3 +94,27 @@ def test_batch_with_empty_work_queues(prec):
         dp.Sigma.fill_(float("nan"))
         assert gu.run_sse(dp, prec=prec, tile_e=[2, 3][i]) == 0
         assert bool((batched == dp.Sigma).all()), i
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batch_of_different_neighbour_counts(prec):
+    """Instances with 1, 50 (the ABI's largest count) and 7 neighbours per
+    atom in one launch; each against the oracle and bitwise against itself
+    alone."""
+    fp32 = prec != 0
+    probs = [configs.Problem(NA=9, NB=1, Norb=4, Nkz=3, Nqz=2, NE=14, Nw=3),
+             configs.Problem(NA=51, NB=50, Norb=4, Nkz=2, Nqz=2, NE=6, Nw=3),
+             configs.Problem(NA=12, NB=7, Norb=4, Nkz=3, Nqz=3, NE=9, Nw=5)]
+    dps = [gu.DeviceProblem(p, 600 + i, ncomp=2, fp32=fp32, scaled=fp32)
+           for i, p in enumerate(probs)]
+    tiles = [3, 2, 4]
+    assert run_batch(dps, prec, tile_e=tiles) == 0
+    for i, dp in enumerate(dps):
+        for c in range(2):
+            e = gu.rel_fro(dp.sigma_host(c), gu.oracle_full(dp, c))
+            print(f"  inst {i} {dp.prob} comp {c}: rel_fro={e:.3e}", flush=True)
+            assert e <= TOL[prec]
+        batched = dp.Sigma.clone()
+        dp.Sigma.fill_(float("nan"))
+        assert gu.run_sse(dp, prec=prec, tile_e=tiles[i]) == 0
+        assert bool((batched == dp.Sigma).all()), i

@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--batch", default="fp64,bf16x3",
                     help="precisions of the 48-instance batched run ('' = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=200.0)
+    ap.add_argument("--batch-small", type=int, default=48,
+                    help="instances of each small-instance batch (tiny and small mixes), "
+                         "one persistent launch against one submission each (0 = skip)")
     ap.add_argument("--serving-jobs", type=int, default=24,
                     help="jobs of the saturated serving run (0 = skip the serving section)")
     ap.add_argument("--serving-half-jobs", type=int, default=8,
@@ -430,6 +433,71 @@ def batch_section(args, torch, sse, configs, DeviceProblem, log):
         if one_by_one is not None:
             out[name]["wave0_one_by_one_s"] = round(one_by_one, 3)
             out[name]["wave0_persistent_speedup"] = round(one_by_one / wave_s[0], 3)
+    if args.batch_small > 0:
+        out["small_instances"] = small_batch_section(args, torch, sse, configs, DeviceProblem,
+                                                     log)
+    return out
+
+
+def small_batch_section(args, torch, sse, configs, DeviceProblem, log):
+    """Batches of instances too small to fill the GPU alone: one persistent
+    launch for the whole batch against one submission per instance, all
+    enqueued back to back on one stream (plans and workspaces made beforehand,
+    one untimed pass of each first)."""
+    mixes = {
+        "tiny": (configs.tiny_instances(configs.SEED + 5, args.batch_small),
+                 "NA ~ U{8..16}, NE ~ U{30..60}, Nw ~ U{4..10}, Nkz = Nqz = 3: fewer output "
+                 "tiles per instance than the GPU has compute units"),
+        "small": (configs.small_instances(configs.SEED + 3, args.batch_small),
+                  "NA ~ U{64..160}, NE ~ U{200..320}, Nw ~ U{10..20}, Nkz = Nqz = 5"),
+    }
+    out = {}
+    stream = torch.cuda.current_stream()
+    for mix, (insts, sizes) in mixes.items():
+        out[mix] = {"instances": len(insts), "sizes": sizes}
+        for name in [x for x in args.batch.split(",") if x]:
+            prec = {"fp64": sse.FP64, "fp32": sse.FP32, "bf16x3": sse.BF16X3}[name]
+            dps = [DeviceProblem(p, 7000 + i, ncomp=1, fp32=prec != sse.FP64)
+                   for i, p in enumerate(insts)]
+            descs = [sse.make_desc(p.NA, p.NB, p.Norb, p.Nkz, p.Nqz, p.NE, p.Nw, prec=prec)
+                     for p in insts]
+            items = [(d.neigh, d.dH, d.G, d.D, d.Sigma) for d in dps]
+            plan = sse.sse_plan_batch(descs, [p.shifts() for p in insts])
+            ws = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+            plans = [sse.sse_plan(d, p.shifts()) for d, p in zip(descs, insts)]
+            wss = [torch.empty(max(pl.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+                   for pl in plans]
+
+            def persistent():
+                return [sse.sse_submit(plan, items, ws, stream)]
+
+            def one_by_one():
+                return [sse.sse_submit(pl, [it], w, stream)
+                        for pl, it, w in zip(plans, items, wss)]
+
+            res = {}
+            for key, run in (("persistent", persistent), ("one_by_one", one_by_one)):
+                for t in run():  # untimed pass
+                    sse.sse_wait(t)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                tickets = run()
+                e1.record(stream)
+                for t in tickets:
+                    sse.sse_wait(t)
+                e1.synchronize()
+                res[key] = e0.elapsed_time(e1)
+            flops = sum(p.flops() for p in insts)
+            out[mix][name] = {"persistent_ms": round(res["persistent"], 3),
+                              "one_by_one_ms": round(res["one_by_one"], 3),
+                              "persistent_gflops": round(flops / res["persistent"] / 1e6, 1),
+                              "speedup": round(res["one_by_one"] / res["persistent"], 2)}
+            log(f"batch {mix} {name}: persistent {res['persistent']:.2f} ms, one by one "
+                f"{res['one_by_one']:.2f} ms")
+            del dps, ws, wss, items, plans, plan
+            torch.cuda.empty_cache()
     return out
 
 

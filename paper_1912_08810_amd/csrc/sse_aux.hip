@@ -30,6 +30,29 @@ __global__ void k_validate_neigh(const int32_t *__restrict__ neigh, int64_t n, i
         atomicOr(status, kStatusBadNeigh);
 }
 
+// The tables of a batch: blockIdx.y selects the table.
+struct NeighBatch {
+    const int32_t *neigh[kMaxBatch];
+    int64_t n[kMaxBatch];
+    int32_t NA[kMaxBatch];
+};
+
+__global__ void k_validate_neigh_batch(const NeighBatch nb, uint32_t *status)
+{
+    const int t = blockIdx.y;
+    const int32_t *__restrict__ neigh = nb.neigh[t];
+    const int64_t n = nb.n[t];
+    const int32_t NA = nb.NA[t];
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = neigh[i];
+        bad |= (f < 0 || f >= NA);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0)
+        atomicOr(status, kStatusBadNeigh);
+}
+
 }  // namespace
 
 hipError_t launch_clear_status(uint32_t *status, hipStream_t s)
@@ -56,6 +79,29 @@ hipError_t launch_validate_neigh(const int32_t *neigh, int64_t n, int32_t NA, ui
         g = 1;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_validate_neigh, dim3((unsigned)g), dim3(256), 0, s, neigh, n, NA, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_neigh_batch(const int32_t *const *neigh, const int64_t *n,
+                                       const int32_t *NA, int count, uint32_t *status,
+                                       hipStream_t s)
+{
+    if (count < 1 || count > kMaxBatch)
+        return hipErrorInvalidValue;
+    NeighBatch nb{};
+    int64_t nmax = 1;
+    for (int t = 0; t < count; ++t) {
+        nb.neigh[t] = neigh[t];
+        nb.n[t] = n[t];
+        nb.NA[t] = NA[t];
+        nmax = n[t] > nmax ? n[t] : nmax;
+    }
+    int64_t g = (nmax + 255) / 256;
+    if (g > 1024)
+        g = 1024;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_validate_neigh_batch, dim3((unsigned)g, (unsigned)count), dim3(256), 0,
+                       s, nb, status);
     return hipGetLastError();
 }
 

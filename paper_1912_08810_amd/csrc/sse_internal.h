@@ -293,6 +293,11 @@ hipError_t launch_clear_status(uint32_t *status, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_validate_neigh(const int32_t *neigh, int64_t n, int32_t NA, uint32_t *status,
                                  hipStream_t s);
+// The same check for the count (<= kMaxBatch) tables of a batch in one launch:
+// table t has n[t] entries that must lie in [0, NA[t]).
+hipError_t launch_validate_neigh_batch(const int32_t *const *neigh, const int64_t *n,
+                                       const int32_t *NA, int count, uint32_t *status,
+                                       hipStream_t s);
 
 constexpr uint32_t kStatusBadNeigh = 1u;
 constexpr uint32_t kStatusBadBlock = 2u;

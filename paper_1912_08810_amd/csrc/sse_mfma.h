@@ -93,6 +93,9 @@ size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int No
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s);
 // bf16x3: n complex64 values of G -> n hi words, then n lo words
 hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t s);
+// the same for the count (<= kMaxBatch) instances of a batch in one launch
+hipError_t mfma_split_batch_launch(const float2 *const *G, void *const *out, const int64_t *n,
+                                   int count, hipStream_t s);
 hipError_t mfma_launch(int prec, const MfmaParams &p, size_t lds_bytes, hipStream_t s);
 hipError_t mfma_persistent_launch(int prec, const BatchLaunch &bl, int grid, size_t lds_bytes,
                                   hipStream_t s);

@@ -545,6 +545,30 @@ __global__ void k_split_g(const float2 *__restrict__ G, uint32_t *__restrict__ o
     }
 }
 
+// The instances of a batch: blockIdx.y selects the instance.
+struct SplitBatch {
+    const float2 *G[kMaxBatch];
+    uint32_t *out[kMaxBatch];
+    int64_t n[kMaxBatch];
+};
+
+__global__ void k_split_g_batch(const SplitBatch sb)
+{
+    const int t = blockIdx.y;
+    const float2 *__restrict__ G = sb.G[t];
+    uint32_t *__restrict__ out = sb.out[t];
+    const int64_t n = sb.n[t];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 v = G[i];
+        uint32_t rh, rl, ih, il;
+        split_bf16(v.x, rh, rl);
+        split_bf16(v.y, ih, il);
+        out[i] = rh | ih << 16;
+        out[n + i] = rl | il << 16;
+    }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kBlock, 1) void k_sse_mfma(const MfmaParams p)
 {
@@ -603,6 +627,29 @@ hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t 
         g = 1;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_split_g, dim3((unsigned)g), dim3(256), 0, s, G, (uint32_t *)out, n);
+    return hipGetLastError();
+}
+
+hipError_t mfma_split_batch_launch(const float2 *const *G, void *const *out, const int64_t *n,
+                                   int count, hipStream_t s)
+{
+    if (count < 1 || count > kMaxBatch)
+        return hipErrorInvalidValue;
+    SplitBatch sb{};
+    int64_t nmax = 1;
+    for (int t = 0; t < count; ++t) {
+        sb.G[t] = G[t];
+        sb.out[t] = (uint32_t *)out[t];
+        sb.n[t] = n[t];
+        nmax = n[t] > nmax ? n[t] : nmax;
+    }
+    // about 65536 workgroups over the batch, at least one per instance
+    int64_t g = (nmax + 255) / 256;
+    const int64_t cap = std::max<int64_t>(1, 65536 / count);
+    if (g > cap)
+        g = cap;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_split_g_batch, dim3((unsigned)g, (unsigned)count), dim3(256), 0, s, sb);
     return hipGetLastError();
 }
 

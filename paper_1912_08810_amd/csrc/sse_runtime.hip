@@ -424,9 +424,17 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
     const int n = (int)P->inst.size();
     const sse_desc &d0 = P->inst[0].d;
     hipError_t e;
-    for (int t = 0; t < n; ++t) {
-        e = launch_validate_neigh(args[t].neigh, (int64_t)P->inst[t].d.NA * P->inst[t].d.NB,
-                                  P->inst[t].d.NA, dstatus, s);
+    {
+        // every instance's neighbour table in one launch
+        const int32_t *tabs[kMaxBatch];
+        int64_t cnt[kMaxBatch];
+        int32_t na[kMaxBatch];
+        for (int t = 0; t < n; ++t) {
+            tabs[t] = args[t].neigh;
+            cnt[t] = (int64_t)P->inst[t].d.NA * P->inst[t].d.NB;
+            na[t] = P->inst[t].d.NA;
+        }
+        e = launch_validate_neigh_batch(tabs, cnt, na, n, dstatus, s);
         if (e != hipSuccess)
             return hip_fail(e, "validate_neigh launch");
     }
@@ -443,6 +451,11 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
             bl.qbeg[x] = P->qbeg[x];
         for (int x = 0; x < kQueues; ++x)
             bl.qcount[x] = P->qcount[x];
+        // bf16x3: every instance's G split in one launch after the loop
+        const float2 *split_in[kMaxBatch];
+        void *split_out[kMaxBatch];
+        int64_t split_n[kMaxBatch];
+        int nsplit = 0;
         for (int t = 0; t < n; ++t) {
             const sse_desc &d = P->inst[t].d;
             const size_t NN = (size_t)d.Norb * d.Norb;
@@ -458,9 +471,10 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
             if (d.prec == SSE_BF16X3) {
                 char *split = ws + P->afrag_off[t] +
                               mfma_split_offset(d.prec, d.NA, d.NB, d.Nqz, P->inst[t].groups);
-                e = mfma_split_launch((const float2 *)bl.ptr[t].G, split, (int64_t)g_elems, s);
-                if (e != hipSuccess)
-                    return hip_fail(e, "G split launch");
+                split_in[nsplit] = (const float2 *)bl.ptr[t].G;
+                split_out[nsplit] = split;
+                split_n[nsplit] = (int64_t)g_elems;
+                ++nsplit;
                 bl.ptr[t].G = split;
             }
             if (!fp64_arith(d.prec)) {
@@ -478,6 +492,11 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
                 if (e != hipSuccess)
                     return hip_fail(e, "MFMA prep launch");
             }
+        }
+        if (nsplit > 0) {
+            e = mfma_split_batch_launch(split_in, split_out, split_n, nsplit, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "G split launch");
         }
         e = launch_clear_u64(counters, kQueues, s);
         if (e != hipSuccess)

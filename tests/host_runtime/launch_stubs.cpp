@@ -83,6 +83,11 @@ hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool, bool, int grid, s
 }
 hipError_t mfma_prep_launch(int, const MfmaPrepParams &, hipStream_t) { return hipSuccess; }
 hipError_t mfma_split_launch(const float2 *, void *, int64_t, hipStream_t) { return hipGetLastError(); }
+hipError_t mfma_split_batch_launch(const float2 *const *, void *const *, const int64_t *, int count,
+                                   hipStream_t)
+{
+    return count >= 1 && count <= kMaxBatch ? hipGetLastError() : hipErrorInvalidValue;
+}
 hipError_t mfma_launch(int, const MfmaParams &, size_t, hipStream_t) { return hipSuccess; }
 hipError_t mfma_persistent_launch(int, const BatchLaunch &bl, int grid, size_t, hipStream_t)
 {
@@ -92,6 +97,11 @@ hipError_t mfma_persistent_launch(int, const BatchLaunch &bl, int grid, size_t, 
 hipError_t launch_clear_status(uint32_t *s, hipStream_t) { *s = 0; return hipGetLastError(); }
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t) { for (int i = 0; i < n; ++i) p[i] = 0; return hipSuccess; }
 hipError_t launch_validate_neigh(const int32_t *, int64_t, int32_t, uint32_t *, hipStream_t) { return hipSuccess; }
+hipError_t launch_validate_neigh_batch(const int32_t *const *, const int64_t *, const int32_t *,
+                                       int count, uint32_t *, hipStream_t)
+{
+    return count >= 1 && count <= kMaxBatch ? hipSuccess : hipErrorInvalidValue;
+}
 hipError_t check_launch(const CheckParams &p, double *out, hipStream_t) { out[0] = 1e-12; out[1] = 1.0; return hipSuccess; }
 }
 namespace sse {

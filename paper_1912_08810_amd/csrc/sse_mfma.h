@@ -91,6 +91,9 @@ size_t mfma_split_offset(int prec, int NA, int NB, int Nqz, const GroupTable &g)
 size_t mfma_aux_bytes(int prec, int NA, int NB, int Nqz, int Nkz, int NE, int Norb,
                       const GroupTable &g);
 hipError_t mfma_prep_launch(int prec, const MfmaPrepParams &p, hipStream_t s);
+// the A fragments of the count instances of a batch in one launch (tables from
+// bl.params, D~ and fragment buffers from bl.ptr)
+hipError_t mfma_prep_batch_launch(int prec, const BatchLaunch &bl, int count, hipStream_t s);
 // bf16x3: n complex64 values of G -> n hi words, then n lo words
 hipError_t mfma_split_launch(const float2 *G, void *out, int64_t n, hipStream_t s);
 // the same for the count (<= kMaxBatch) instances of a batch in one launch

@@ -92,46 +92,51 @@ __device__ __forceinline__ void split_bf16(float x, uint32_t &hi, uint32_t &lo)
 }
 
 // A-operand value of MFMA row r for tap t, K component x (0 = re, 1 = im).
-__device__ __forceinline__ float a_value(const MfmaPrepParams &p, int ab, int q, int row, int t,
+__device__ __forceinline__ float a_value(const float2 *D, int NA, int NB, int Nw,
+                                         const TapTable &taps, int ab, int q, int row, int t,
                                          int tend, int x)
 {
     const int ij = row >> 1, ri = row & 1;
     if (ij >= kNF || t >= tend)
         return 0.0f;
-    const float2 d = p.D[(((size_t)q * p.Nw + p.taps.w[t]) * p.NA * p.NB + ab) * kNF + ij];
+    const float2 d = D[(((size_t)q * Nw + taps.w[t]) * NA * NB + ab) * kNF + ij];
     if (ri == 0)
         return x == 0 ? d.x : -d.y;
     return x == 0 ? d.y : d.x;
 }
 
-// One thread per (a, b, q, group, lane): the lane's 32-byte A fragment.
+// Item idx of the A-fragment preparation of one instance: the first
+// kZeroPage / 16 items also clear the zero page; item (a, b, q, group, lane)
+// writes the lane's 32-byte A fragment.  The tables are the instance's (a
+// kernel argument, or a batch's table in global memory).
 template <int PREC>
-__global__ void k_prep_afrag(const MfmaPrepParams p)
+__device__ __forceinline__ void prep_item(int64_t idx, const float2 *D, void *afrag, void *zero,
+                                          int NA, int NB, int Nqz, int Nw, const TapTable &taps,
+                                          const GroupTable &groups)
 {
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx < (int64_t)(kZeroPage / 16))
-        reinterpret_cast<uint4 *>(p.zero)[idx] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4 *>(zero)[idx] = make_uint4(0u, 0u, 0u, 0u);
     const int lane = (int)(idx & 63);
     int64_t rest = idx >> 6;
-    const int g = (int)(rest % p.groups.n);
-    rest /= p.groups.n;
-    const int q = (int)(rest % p.Nqz);
-    const int64_t ab = rest / p.Nqz;
-    if (ab >= (int64_t)p.NA * p.NB)
+    const int g = (int)(rest % groups.n);
+    rest /= groups.n;
+    const int q = (int)(rest % Nqz);
+    const int64_t ab = rest / Nqz;
+    if (ab >= (int64_t)NA * NB)
         return;
     int c = 0;
-    while (p.groups.gb[c + 1] <= g)
+    while (groups.gb[c + 1] <= g)
         ++c;
-    const int tend = p.taps.cb[c + 1];
-    const int t0 = p.groups.t0[g];
+    const int tend = taps.cb[c + 1];
+    const int t0 = groups.t0[g];
     const int row = lane & 31, h = lane >> 5;
-    uint4 *out = reinterpret_cast<uint4 *>(p.afrag) + (idx << 1);
+    uint4 *out = reinterpret_cast<uint4 *>(afrag) + (idx << 1);
     if (PREC == SSE_BF16X3) {
         uint32_t hi[8], lo[8];
         for (int u = 0; u < 4; ++u)
             for (int x = 0; x < 2; ++x)
-                split_bf16(a_value(p, (int)ab, q, row, t0 + 4 * h + u, tend, x), hi[2 * u + x],
-                           lo[2 * u + x]);
+                split_bf16(a_value(D, NA, NB, Nw, taps, (int)ab, q, row, t0 + 4 * h + u, tend, x),
+                           hi[2 * u + x], lo[2 * u + x]);
         out[0] = make_uint4(hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16,
                             hi[6] | hi[7] << 16);
         out[1] = make_uint4(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16,
@@ -139,12 +144,39 @@ __global__ void k_prep_afrag(const MfmaPrepParams p)
     } else {
         float v[8];
         for (int u = 0; u < 8; ++u)
-            v[u] = a_value(p, (int)ab, q, row, t0 + u, tend, h);
+            v[u] = a_value(D, NA, NB, Nw, taps, (int)ab, q, row, t0 + u, tend, h);
         out[0] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                             __float_as_uint(v[3]));
         out[1] = make_uint4(__float_as_uint(v[4]), __float_as_uint(v[5]), __float_as_uint(v[6]),
                             __float_as_uint(v[7]));
     }
+}
+
+// One thread per (a, b, q, group, lane): the lane's 32-byte A fragment.
+template <int PREC>
+__global__ void k_prep_afrag(const MfmaPrepParams p)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    prep_item<PREC>(idx, p.D, p.afrag, p.zero, p.NA, p.NB, p.Nqz, p.Nw, p.taps, p.groups);
+}
+
+// The A fragments of every instance of a batch in one launch: blockIdx.y is
+// the instance (sizes and tables from the batch's parameter table, D~ and the
+// fragment buffer from the launch's pointers); each instance's items are
+// strided over the grid's x extent.
+template <int PREC>
+__global__ void k_prep_afrag_batch(const BatchLaunch bl)
+{
+    const int t = blockIdx.y;
+    const MfmaParams &mp = reinterpret_cast<const MfmaParams *>(bl.params)[t];
+    const int NA = mp.NA, NB = mp.NB, Nqz = mp.Nqz, Nw = mp.Nw;
+    const int64_t n = std::max<int64_t>((int64_t)NA * NB * Nqz * mp.groups.n * 64,
+                                        (int64_t)(kZeroPage / 16));
+    const float2 *D = reinterpret_cast<const float2 *>(bl.ptr[t].D);
+    char *aux = reinterpret_cast<char *>(const_cast<void *>(bl.ptr[t].aux));
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        prep_item<PREC>(idx, D, aux + kZeroPage, aux, NA, NB, Nqz, Nw, mp.taps, mp.groups);
 }
 
 // One output tile (energies [et TE, et TE + TE) of (k, a)); pp supplies sizes and
@@ -650,6 +682,20 @@ hipError_t mfma_split_batch_launch(const float2 *const *G, void *const *out, con
         g = cap;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_split_g_batch, dim3((unsigned)g, (unsigned)count), dim3(256), 0, s, sb);
+    return hipGetLastError();
+}
+
+hipError_t mfma_prep_batch_launch(int prec, const BatchLaunch &bl, int count, hipStream_t s)
+{
+    if (count < 1 || count > kMaxBatch)
+        return hipErrorInvalidValue;
+    (void)hipGetLastError();
+    if (prec == SSE_BF16X3)
+        hipLaunchKernelGGL(k_prep_afrag_batch<SSE_BF16X3>, dim3(1024, (unsigned)count), dim3(256),
+                           0, s, bl);
+    else
+        hipLaunchKernelGGL(k_prep_afrag_batch<SSE_FP32>, dim3(1024, (unsigned)count), dim3(256),
+                           0, s, bl);
     return hipGetLastError();
 }
 

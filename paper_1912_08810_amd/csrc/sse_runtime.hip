@@ -477,26 +477,17 @@ sse_status enqueue_batch(sse_plan_s *P, const sse_args *args, char *ws, uint32_t
                 ++nsplit;
                 bl.ptr[t].G = split;
             }
-            if (!fp64_arith(d.prec)) {
-                MfmaPrepParams pp{};
-                pp.D = (const float2 *)bl.ptr[t].D;
-                pp.zero = ws + P->afrag_off[t];
-                pp.afrag = ws + P->afrag_off[t] + mfmak::kZeroPage;
-                pp.NA = d.NA;
-                pp.NB = d.NB;
-                pp.Nqz = d.Nqz;
-                pp.Nw = d.Nw;
-                pp.taps = P->inst[t].taps;
-                pp.groups = P->inst[t].groups;
-                e = mfma_prep_launch(d.prec, pp, s);
-                if (e != hipSuccess)
-                    return hip_fail(e, "MFMA prep launch");
-            }
         }
         if (nsplit > 0) {
             e = mfma_split_batch_launch(split_in, split_out, split_n, nsplit, s);
             if (e != hipSuccess)
                 return hip_fail(e, "G split launch");
+        }
+        if (!fp64_arith(d0.prec)) {
+            // every instance's A fragments in one launch
+            e = mfma_prep_batch_launch(d0.prec, bl, n, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "MFMA prep launch");
         }
         e = launch_clear_u64(counters, kQueues, s);
         if (e != hipSuccess)

@@ -82,6 +82,10 @@ hipError_t fp64_persistent_launch(const BatchLaunch &bl, bool, bool, int grid, s
     return hipSuccess;
 }
 hipError_t mfma_prep_launch(int, const MfmaPrepParams &, hipStream_t) { return hipSuccess; }
+hipError_t mfma_prep_batch_launch(int, const BatchLaunch &, int count, hipStream_t)
+{
+    return count >= 1 && count <= kMaxBatch ? hipSuccess : hipErrorInvalidValue;
+}
 hipError_t mfma_split_launch(const float2 *, void *, int64_t, hipStream_t) { return hipGetLastError(); }
 hipError_t mfma_split_batch_launch(const float2 *const *, void *const *, const int64_t *, int count,
                                    hipStream_t)
